@@ -1,0 +1,153 @@
+/*
+ * aop.h -- C ABI of libaop, an MI355X (gfx950) library that prices American
+ * options with the FFT-based nonlinear 1D stencil of Ahmad et al., "Fast
+ * American Option Pricing using Nonlinear Stencils" (arXiv 2303.02317).
+ *
+ * Problem statement (Fig. 1, Table 1 notation): given spot S, strike K,
+ * risk-free rate R, dividend yield Y, volatility V, time to expiry E and the
+ * number of time steps T, return the option value at the root of
+ *   - the binomial (CRR) lattice, American call          (Sec. 2, Def. 2.1),
+ *   - the trinomial lattice, American call                (Sec. 3),
+ *   - the explicit finite-difference BSM grid, American put (Sec. 4, eq. bsmG).
+ * E is in years; dt = E/T.  The BSM grid uses s = ln(x/K), tau = sigma^2 t / 2,
+ * dtau = sigma^2 E / (2T), ds = sqrt(dtau / lambda), centred on s0 = ln(S/K).
+ *
+ * The method (Sec. 2.3, Sec. 3, Sec. 4.3): a red (continuation) segment is
+ * advanced many rows at once by correlating it with the h-step stencil kernel
+ * through FFTs; the red/green boundary, which moves at most one cell per row
+ * (Corollary 2.6, Theorem 4.2), is tracked by recursive trapezoid
+ * decomposition whose base case is a narrow band of the direct
+ * max(continuation, exercise) stencil.  Work O(T log^2 T), span O(T).
+ *
+ * Conventions
+ *   - Pointers named d_* are device (HBM) pointers; h_* are host pointers.
+ *   - Nothing here allocates device memory except aop_ctx_create (twiddle
+ *     table) and the synchronous helper aop_price; batch calls use the
+ *     caller's workspace of at least aop_workspace_bytes() bytes.
+ *   - All functions return an aop_status; nothing throws across the ABI.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - Ties between continuation and exercise value count as continuation
+ *     (Def. 2.1: red when G^red >= G^green).  A cell whose exercise value is
+ *     not finite is an exercise cell.
+ */
+#ifndef AOP_H
+#define AOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AOP_BINOMIAL_CALL = 0,  /* Sec. 2: CRR lattice, American call with dividend yield */
+    AOP_TRINOMIAL_CALL = 1, /* Sec. 3: trinomial lattice, American call */
+    AOP_BSM_PUT = 2         /* Sec. 4: explicit FD grid of the BSM PDE, American put (Y = 0) */
+} aop_model;
+
+typedef enum {
+    AOP_FP64 = 0,  /* every step in IEEE double precision */
+    AOP_MIXED = 1  /* FFT convolutions in FP32 split (hi/lo) arithmetic; boundary
+                      search, band stencil and root accumulation in FP64 */
+} aop_precision;
+
+typedef enum {
+    AOP_OK = 0,
+    AOP_EINVAL = 1,    /* non-finite or non-positive S, K, V, E; T < 1; unknown model;
+                          Y != 0 for the BSM put; bad lambda */
+    AOP_EPROB = 2,     /* lattice probability outside (0,1) or a BSM scheme
+                          coefficient negative (explicit-scheme stability) */
+    AOP_ENOMEM = 3,    /* workspace too small / allocation failed */
+    AOP_EDEVICE = 4,   /* HIP runtime error */
+    AOP_ETOOBIG = 5,   /* T above AOP_MAX_T */
+    AOP_ECANCELED = 6, /* not priced: earlier failure in the same call */
+    AOP_ENOTIMPL = 7   /* the requested precision is not available for this model */
+} aop_status;
+
+#define AOP_MAX_T (1LL << 21)
+
+/* One option (host memory).  flags: reserved, must be 0. */
+typedef struct {
+    int32_t model;   /* aop_model */
+    int32_t flags;
+    double S0;       /* spot */
+    double K;        /* strike */
+    double r;        /* risk-free rate, continuously compounded, per year */
+    double q;        /* dividend yield per year (must be 0 for AOP_BSM_PUT) */
+    double sigma;    /* volatility per sqrt(year) */
+    double expiry;   /* years */
+    int64_t T;       /* time steps, 1 <= T <= AOP_MAX_T */
+} aop_option;
+
+typedef struct aop_ctx aop_ctx;
+
+/* Create a context on HIP device `device`: allocates and fills the FFT
+ * twiddle table (about 64 MB) and a pinned staging buffer.  The context
+ * owns these until aop_ctx_destroy.  lambda = dtau/ds^2 of the BSM grid
+ * (pass 0 for the default 1/3). */
+aop_status aop_ctx_create(int device, double lambda, aop_ctx **out);
+aop_status aop_ctx_destroy(aop_ctx *ctx);
+
+/* Bytes of device workspace a batch of n options needs (host options).
+ * Invalid options contribute nothing; their status is reported by the
+ * pricing call. */
+aop_status aop_workspace_bytes(const aop_option *h_opts, int64_t n, int32_t precision,
+                               size_t *bytes);
+
+/* Validate one option and report its status without pricing it. */
+aop_status aop_validate(const aop_option *h_opt, double lambda);
+
+/*
+ * Price n options with the FFT nonlinear-stencil method, asynchronously on
+ * `hip_stream` (a hipStream_t; NULL = default stream).
+ *   h_opts      host array of n options (read before return).
+ *   d_workspace device buffer of ws_bytes >= aop_workspace_bytes(); must stay
+ *               alive and untouched until the stream reaches this work.
+ *   d_price     device array of n doubles: the price of each option (NaN for
+ *               an option whose status is not AOP_OK).
+ *   h_status    host array of n int32 (written before return): AOP_OK or the
+ *               validation error of each option.
+ *   d_boundary  NULL, or a device array of n * boundary_stride int64 with
+ *               boundary_stride >= max T + 1.  Row i (lattices) or step n (BSM)
+ *               of option o goes to d_boundary[o * boundary_stride + i]:
+ *               lattices: the last continuation column of row i, -1 if none;
+ *               BSM: the last exercise offset k of step n, INT64_MIN if none.
+ *               Rows the method never visits individually are exact too: every
+ *               row is either walked by the band stencil or produced by it.
+ * Returns AOP_OK when the batch was launched (per-option failures are in
+ * h_status), AOP_ENOMEM if ws_bytes is too small, AOP_EDEVICE on HIP errors.
+ */
+aop_status aop_price_batch(aop_ctx *ctx, const aop_option *h_opts, int64_t n, int32_t precision,
+                           void *d_workspace, size_t ws_bytes, double *d_price,
+                           int32_t *h_status, int64_t *d_boundary, int64_t boundary_stride,
+                           void *hip_stream);
+
+/*
+ * Comparison path: the plain Theta(T^2) backward induction of Fig. 1 on the
+ * GPU (same arguments and semantics as aop_price_batch, FP64 only; the
+ * boundary is not reported: pass NULL).  Workspace: aop_plain_workspace_bytes.
+ */
+aop_status aop_plain_workspace_bytes(const aop_option *h_opts, int64_t n, size_t *bytes);
+aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *h_opts, int64_t n,
+                                 void *d_workspace, size_t ws_bytes, double *d_price,
+                                 int32_t *h_status, void *hip_stream);
+
+/* Synchronous convenience: price one option, allocating and freeing its own
+ * workspace.  h_boundary: NULL or a host array of T+1 int64. */
+aop_status aop_price(aop_ctx *ctx, const aop_option *h_opt, int32_t precision, double *h_price,
+                     int64_t *h_boundary);
+
+/* Wait for all work on hip_stream. */
+aop_status aop_sync(void *hip_stream);
+
+const char *aop_status_str(aop_status s);
+
+/* Library version string. */
+const char *aop_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AOP_H */

@@ -1,0 +1,210 @@
+"""Thin Python binding of libaop's C ABI (include/aop.h).
+
+Argument marshalling only: every pricing step runs in the gfx950 kernels of
+``libaop.so``.  PyTorch provides device memory (workspace, outputs) and the
+HIP stream.  Importing this module never falls back to anything else: if the
+library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaop.so")
+
+AOP_BINOMIAL_CALL, AOP_TRINOMIAL_CALL, AOP_BSM_PUT = 0, 1, 2
+AOP_FP64, AOP_MIXED = 0, 1
+STATUS = {0: "ok", 1: "EINVAL", 2: "EPROB", 3: "ENOMEM", 4: "EDEVICE", 5: "ETOOBIG", 6: "ECANCELED",
+          7: "ENOTIMPL"}
+BSM_NONE = np.iinfo(np.int64).min
+
+#: Every symbol include/aop.h declares.
+EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
+           "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_price", "aop_sync", "aop_status_str",
+           "aop_version"]
+
+
+class AopError(RuntimeError):
+    pass
+
+
+class AopOption(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("flags", ctypes.c_int32), ("S0", ctypes.c_double),
+                ("K", ctypes.c_double), ("r", ctypes.c_double), ("q", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("expiry", ctypes.c_double), ("T", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libaop.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise AopError("libaop.so is not built (run __graft_entry__.build()); there is no fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "aop_ctx_create": (I32, [ctypes.c_int, D, ctypes.POINTER(P)]),
+        "aop_ctx_destroy": (I32, [P]),
+        "aop_workspace_bytes": (I32, [P, I64, I32, ctypes.POINTER(SZ)]),
+        "aop_validate": (I32, [P, D]),
+        "aop_price_batch": (I32, [P, P, I64, I32, P, SZ, P, P, P, I64, P]),
+        "aop_plain_workspace_bytes": (I32, [P, I64, ctypes.POINTER(SZ)]),
+        "aop_price_batch_plain": (I32, [P, P, I64, P, SZ, P, P, P]),
+        "aop_price": (I32, [P, P, I32, ctypes.POINTER(D), P]),
+        "aop_sync": (I32, [P]),
+        "aop_status_str": (ctypes.c_char_p, [I32]),
+        "aop_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise AopError("%s failed: %s" % (what, load().aop_status_str(rc).decode()))
+
+
+def options_array(opts) -> ctypes.Array:
+    arr = (AopOption * max(1, len(opts)))()
+    for i, o in enumerate(opts):
+        arr[i] = AopOption(int(o["model"]), 0, float(o["S0"]), float(o["K"]), float(o["r"]), float(o["q"]),
+                           float(o["sigma"]), float(o["expiry"]), int(o["T"]))
+    return arr
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An aop_ctx on one device (owns the twiddle table and a pinned staging buffer)."""
+
+    def __init__(self, device: int = 0, lam: float = 1.0 / 3.0):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        _check(lib.aop_ctx_create(int(device), float(lam), ctypes.byref(self._h)), "aop_ctx_create")
+        self.device = device
+        self.lam = lam
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().aop_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(opts, precision: int = AOP_FP64) -> int:
+    arr = options_array(opts)
+    n = ctypes.c_size_t()
+    _check(load().aop_workspace_bytes(arr, len(opts), int(precision), ctypes.byref(n)), "aop_workspace_bytes")
+    return n.value
+
+
+def plain_workspace_bytes(opts) -> int:
+    arr = options_array(opts)
+    n = ctypes.c_size_t()
+    _check(load().aop_plain_workspace_bytes(arr, len(opts), ctypes.byref(n)), "aop_plain_workspace_bytes")
+    return n.value
+
+
+def validate(opt, lam: float = 1.0 / 3.0) -> int:
+    return int(load().aop_validate(options_array([opt]), float(lam)))
+
+
+@dataclass
+class Launch:
+    """Device outputs of one asynchronous batch launch."""
+    price: "object"      # torch float64 tensor [n] on the device
+    status: np.ndarray   # host int32 [n]
+    boundary: "object"   # torch int64 tensor [n, stride] or None
+    workspace: "object"  # torch uint8 tensor (kept alive until the stream passes)
+
+
+def launch_batch(ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = False, stream=None,
+                 workspace=None) -> Launch:
+    """Enqueue pricing of ``opts`` on ``stream``; returns device tensors (no sync)."""
+    import torch
+
+    lib = load()
+    n = len(opts)
+    dev = torch.device("cuda", ctx.device)
+    arr = options_array(opts)
+    need = workspace_bytes(opts, precision)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    stride = max(int(o["T"]) for o in opts) + 1 if (boundary and n) else 0
+    bnd = torch.empty((max(n, 1), max(stride, 1)), dtype=torch.int64, device=dev) if boundary else None
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib.aop_price_batch(ctx.handle, arr, n, int(precision), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel(), ctypes.c_void_p(price.data_ptr()),
+                             status.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.c_void_p(bnd.data_ptr()) if bnd is not None else None, stride,
+                             _stream_handle(stream))
+    _check(rc, "aop_price_batch")
+    return Launch(price[:n], status[:n], bnd[:n] if bnd is not None else None, workspace)
+
+
+def price_batch(ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = False, stream=None):
+    """Price a batch and wait: returns (prices, status, boundaries or None) as numpy arrays."""
+    import torch
+
+    L = launch_batch(ctx, opts, precision, boundary, stream)
+    (stream or torch.cuda.current_stream()).synchronize()
+    b = L.boundary.cpu().numpy() if L.boundary is not None else None
+    return L.price.cpu().numpy(), L.status.copy(), b
+
+
+def launch_plain(ctx: Context, opts, stream=None, workspace=None):
+    """Enqueue the plain Theta(T^2) GPU stencil on ``opts`` (comparison path)."""
+    import torch
+
+    lib = load()
+    n = len(opts)
+    dev = torch.device("cuda", ctx.device)
+    arr = options_array(opts)
+    need = plain_workspace_bytes(opts)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib.aop_price_batch_plain(ctx.handle, arr, n, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   ctypes.c_void_p(price.data_ptr()), status.ctypes.data_as(ctypes.c_void_p),
+                                   _stream_handle(stream))
+    _check(rc, "aop_price_batch_plain")
+    return Launch(price[:n], status[:n], None, workspace)
+
+
+def price_one(ctx: Context, opt, precision: int = AOP_FP64, boundary: bool = False):
+    """Synchronous single option through aop_price (the library allocates)."""
+    lib = load()
+    out = ctypes.c_double()
+    b = np.empty(int(opt["T"]) + 1, dtype=np.int64) if boundary else None
+    rc = lib.aop_price(ctx.handle, options_array([opt]), int(precision), ctypes.byref(out),
+                       b.ctypes.data_as(ctypes.c_void_p) if b is not None else None)
+    _check(rc, "aop_price")
+    return (out.value, b) if boundary else out.value

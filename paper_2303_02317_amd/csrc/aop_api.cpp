@@ -1,0 +1,350 @@
+// aop_api.cpp -- host side of libaop's C ABI (declared in include/aop.h).
+//
+// Validates options, derives the lattice / grid parameters from the paper's
+// formulas (Fig. 1 and Sec. 2.1 for the binomial lattice, Sec. 3 for the
+// trinomial lattice, eq. (bsmG) of Sec. 4.2 for the BSM grid), lays out the
+// caller's device workspace and launches the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "aop.h"
+#include "aop_internal.h"
+
+using aop::Desc;
+
+struct aop_ctx {
+    int device = 0;
+    double lambda = 1.0 / 3.0;
+    void *d_tw = nullptr;          // twiddle table, TW_N complex doubles
+    Desc *h_stage = nullptr;       // pinned staging for descriptors
+    size_t stage_cap = 0;          // descriptors
+    hipEvent_t stage_done = nullptr;
+    bool stage_pending = false;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+inline int64_t next_pow2(int64_t n)
+{
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Fill the model parameters of a descriptor; returns an aop_status.
+aop_status make_desc(const aop_option &o, double lambda, Desc &d)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.model = -1;
+    if (!(std::isfinite(o.S0) && std::isfinite(o.K) && std::isfinite(o.r) && std::isfinite(o.q) &&
+          std::isfinite(o.sigma) && std::isfinite(o.expiry)))
+        return AOP_EINVAL;
+    if (o.S0 <= 0 || o.K <= 0 || o.sigma <= 0 || o.expiry <= 0 || o.q < 0 || o.T < 1 || o.flags != 0)
+        return AOP_EINVAL;
+    if (o.T > AOP_MAX_T) return AOP_ETOOBIG;
+    const double T = (double)o.T;
+    d.T = o.T;
+    d.S = o.S0;
+    d.K = o.K;
+    switch (o.model) {
+    case AOP_BINOMIAL_CALL: {
+        // Fig. 1: dt = E/T, u = e^{V sqrt(dt)}, d = 1/u, p = (e^{(R-Y)dt} - d)/(u - d), m = e^{-R dt};
+        // Sec. 2.1: s0 = m(1-p) on the down child G[i+1][j], s1 = mp on the up child G[i+1][j+1].
+        const double dt = o.expiry / T;
+        const double a = o.sigma * std::sqrt(dt);
+        const double u = std::exp(a), dn = 1.0 / u;
+        const double p = (std::exp((o.r - o.q) * dt) - dn) / (u - dn);
+        const double m = std::exp(-o.r * dt);
+        if (!(p > 0.0 && p < 1.0)) return AOP_EPROB;
+        d.a = a;
+        d.no_green = (o.q == 0.0);
+        d.w0 = m * (1.0 - p);
+        d.w1 = m * p;
+        d.w2 = 0.0;
+        break;
+    }
+    case AOP_TRINOMIAL_CALL: {
+        // Sec. 3: u = e^{V sqrt(2 dt)}, p_u = ((e^{(R-Y)dt/2} - sqrt d)/(sqrt u - sqrt d))^2,
+        // p_d = ((sqrt u - e^{(R-Y)dt/2})/(sqrt u - sqrt d))^2, p_o = 1 - p_u - p_d;
+        // children j (down, m p_d), j+1 (same, m p_o), j+2 (up, m p_u).
+        const double dt = o.expiry / T;
+        const double A = o.sigma * std::sqrt(2.0 * dt);
+        const double su = std::exp(0.5 * A), sd = std::exp(-0.5 * A);
+        const double g = std::exp(0.5 * (o.r - o.q) * dt);
+        const double pu = ((g - sd) / (su - sd)) * ((g - sd) / (su - sd));
+        const double pd = ((su - g) / (su - sd)) * ((su - g) / (su - sd));
+        const double po = 1.0 - pu - pd;
+        const double m = std::exp(-o.r * dt);
+        if (!(pu > 0.0 && pd > 0.0 && po >= 0.0)) return AOP_EPROB;
+        d.a = A;
+        d.no_green = (o.q == 0.0);
+        d.w0 = m * pd;
+        d.w1 = m * po;
+        d.w2 = m * pu;
+        break;
+    }
+    case AOP_BSM_PUT: {
+        // Sec. 4.2: s = ln(x/K), tau = sigma^2 (E - t)/2, omega = 2R/sigma^2; eq. (bsmG):
+        // v^{n+1}_k = (1 - omega dtau - 2 dtau/ds^2) v_k + sum_{h=+-1} (dtau/ds^2 + h (omega-1)/2 dtau/ds) v_{k+h}.
+        if (o.q != 0.0) return AOP_EINVAL;
+        if (!(lambda > 0.0 && lambda <= 0.5)) return AOP_EINVAL;
+        const double dtau = 0.5 * o.sigma * o.sigma * o.expiry / T;
+        const double ds = std::sqrt(dtau / lambda);
+        const double omega = 2.0 * o.r / (o.sigma * o.sigma);
+        const double lam = dtau / (ds * ds);
+        const double drift = 0.5 * (omega - 1.0) * dtau / ds;
+        const double ca = lam + drift, cb = lam - drift, cc = 1.0 - omega * dtau - 2.0 * lam;
+        if (!(ca >= 0.0 && cb >= 0.0 && cc >= 0.0)) return AOP_EPROB;
+        d.a = ds;
+        d.s0 = std::log(o.S0 / o.K);
+        d.w0 = cb;  // k-1
+        d.w1 = cc;  // k
+        d.w2 = ca;  // k+1
+        break;
+    }
+    default:
+        return AOP_EINVAL;
+    }
+    d.model = o.model;
+    return AOP_OK;
+}
+
+// Per-option workspace geometry (doubles / complex elements).
+void geometry(Desc &d)
+{
+    const int64_t T = d.T;
+    int64_t nin_max;
+    if (d.model == aop::BINOMIAL) {
+        d.row_len = T + 2;
+        d.arena_len = 2 * d.row_len + 256;
+        nin_max = T;
+    } else if (d.model == aop::TRINOMIAL) {
+        d.row_len = 2 * T + 3;
+        d.arena_len = 2 * d.row_len + 256;
+        nin_max = 2 * T + 1;
+    } else {
+        d.row_len = 3 * T + 3;  // k in [-2T-1, T+1]
+        d.arena_len = 4 * T + 256;
+        nin_max = 2 * T + 1;
+    }
+    d.nfft = std::max<int64_t>(next_pow2(std::max<int64_t>(nin_max, 2)), 2);
+}
+
+size_t option_bytes(const Desc &d)
+{
+    return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.nfft);
+}
+
+// Build descriptors for a batch; returns total workspace bytes.
+size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambda, Desc *out, int32_t *status)
+{
+    size_t off = align_up(sizeof(Desc) * (size_t)std::max<int64_t>(n, 1));
+    for (int64_t i = 0; i < n; ++i) {
+        Desc &d = out[i];
+        aop_status st = make_desc(opts[i], lambda, d);
+        if (st == AOP_OK && prec != AOP_FP64) st = AOP_ENOTIMPL;
+        d.out_index = i;
+        d.prec = prec;
+        if (status) status[i] = st;
+        if (st != AOP_OK) {
+            d.model = -1;
+            continue;
+        }
+        geometry(d);
+        d.ws_off = (int64_t)off;
+        off += option_bytes(d);
+    }
+    return off;
+}
+
+aop_status ensure_stage(aop_ctx *ctx, size_t n)
+{
+    if (ctx->stage_pending) {
+        if (hipEventSynchronize(ctx->stage_done) != hipSuccess) return AOP_EDEVICE;
+        ctx->stage_pending = false;
+    }
+    if (n <= ctx->stage_cap) return AOP_OK;
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    ctx->h_stage = nullptr;
+    ctx->stage_cap = 0;
+    size_t cap = std::max<size_t>(n, 64);
+    if (hipHostMalloc((void **)&ctx->h_stage, cap * sizeof(Desc), hipHostMallocDefault) != hipSuccess)
+        return AOP_ENOMEM;
+    ctx->stage_cap = cap;
+    return AOP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *aop_version(void) { return "aop-mi355x 0.1 (gfx950)"; }
+
+const char *aop_status_str(aop_status s)
+{
+    switch (s) {
+    case AOP_OK: return "ok";
+    case AOP_EINVAL: return "invalid argument";
+    case AOP_EPROB: return "lattice probability or scheme coefficient out of range";
+    case AOP_ENOMEM: return "out of memory / workspace too small";
+    case AOP_EDEVICE: return "HIP device error";
+    case AOP_ETOOBIG: return "T above AOP_MAX_T";
+    case AOP_ECANCELED: return "canceled";
+    case AOP_ENOTIMPL: return "not implemented for this model/precision";
+    }
+    return "unknown status";
+}
+
+aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
+{
+    if (!out) return AOP_EINVAL;
+    *out = nullptr;
+    if (lambda == 0.0) lambda = 1.0 / 3.0;
+    if (!(lambda > 0.0 && lambda <= 0.5)) return AOP_EINVAL;
+    aop_ctx *ctx = new (std::nothrow) aop_ctx;
+    if (!ctx) return AOP_ENOMEM;
+    ctx->device = device;
+    ctx->lambda = lambda;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return AOP_EDEVICE;
+    }
+    if (hipMalloc(&ctx->d_tw, sizeof(double) * 2 * (size_t)aop::TW_N) != hipSuccess) {
+        delete ctx;
+        return AOP_ENOMEM;
+    }
+    if (hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess ||
+        aop::launch_twiddles(ctx->d_tw, nullptr) != 0 || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(ctx->d_tw);
+        delete ctx;
+        return AOP_EDEVICE;
+    }
+    *out = ctx;
+    return AOP_OK;
+}
+
+aop_status aop_ctx_destroy(aop_ctx *ctx)
+{
+    if (!ctx) return AOP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
+    if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+    delete ctx;
+    return AOP_OK;
+}
+
+aop_status aop_validate(const aop_option *o, double lambda)
+{
+    if (!o) return AOP_EINVAL;
+    if (lambda == 0.0) lambda = 1.0 / 3.0;
+    Desc d;
+    return make_desc(*o, lambda, d);
+}
+
+aop_status aop_workspace_bytes(const aop_option *opts, int64_t n, int32_t precision, size_t *bytes)
+{
+    if (!bytes || n < 0 || (n > 0 && !opts)) return AOP_EINVAL;
+    std::vector<Desc> d((size_t)std::max<int64_t>(n, 1));
+    *bytes = build_batch(opts, n, precision, 1.0 / 3.0, d.data(), nullptr);
+    return AOP_OK;
+}
+
+aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int32_t precision,
+                           void *d_ws, size_t ws_bytes, double *d_price, int32_t *h_status,
+                           int64_t *d_bnd, int64_t bnd_stride, void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!opts || !d_ws || !d_price))) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    aop_status st = ensure_stage(ctx, (size_t)n);
+    if (st != AOP_OK) return st;
+    std::vector<int32_t> stat((size_t)n);
+    const size_t need = build_batch(opts, n, precision, ctx->lambda, ctx->h_stage, stat.data());
+    if (h_status) std::memcpy(h_status, stat.data(), sizeof(int32_t) * (size_t)n);
+    if (ws_bytes < need) return AOP_ENOMEM;
+    if (d_bnd) {
+        int64_t tmax = 0;
+        for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, opts[i].T);
+        if (bnd_stride < tmax + 1) return AOP_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(d_ws, ctx->h_stage, sizeof(Desc) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AOP_EDEVICE;
+    if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
+    ctx->stage_pending = true;
+    if (aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr,
+                          stream) != 0)
+        return AOP_EDEVICE;
+    return AOP_OK;
+}
+
+aop_status aop_plain_workspace_bytes(const aop_option *opts, int64_t n, size_t *bytes)
+{
+    (void)opts;
+    (void)n;
+    if (bytes) *bytes = 0;
+    return AOP_ENOTIMPL;
+}
+
+aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *opts, int64_t n, void *d_ws,
+                                 size_t ws_bytes, double *d_price, int32_t *h_status, void *stream)
+{
+    (void)ctx; (void)opts; (void)n; (void)d_ws; (void)ws_bytes; (void)d_price; (void)h_status; (void)stream;
+    return AOP_ENOTIMPL;
+}
+
+aop_status aop_price(aop_ctx *ctx, const aop_option *opt, int32_t precision, double *h_price,
+                     int64_t *h_bnd)
+{
+    if (!ctx || !opt || !h_price) return AOP_EINVAL;
+    size_t bytes = 0;
+    aop_status st = aop_workspace_bytes(opt, 1, precision, &bytes);
+    if (st != AOP_OK) return st;
+    int32_t ost = AOP_OK;
+    {
+        Desc d;
+        ost = make_desc(*opt, ctx->lambda, d);
+        if (ost == AOP_OK && precision != AOP_FP64) ost = AOP_ENOTIMPL;
+        if (ost != AOP_OK) return (aop_status)ost;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    void *ws = nullptr;
+    double *dp = nullptr;
+    int64_t *db = nullptr;
+    const int64_t stride = opt->T + 1;
+    aop_status rc = AOP_OK;
+    if (hipMalloc(&ws, bytes) != hipSuccess || hipMalloc((void **)&dp, sizeof(double)) != hipSuccess ||
+        (h_bnd && hipMalloc((void **)&db, sizeof(int64_t) * (size_t)stride) != hipSuccess)) {
+        rc = AOP_ENOMEM;
+    } else {
+        rc = aop_price_batch(ctx, opt, 1, precision, ws, bytes, dp, &ost, db, stride, nullptr);
+        if (rc == AOP_OK && hipStreamSynchronize(nullptr) != hipSuccess) rc = AOP_EDEVICE;
+        if (rc == AOP_OK && hipMemcpy(h_price, dp, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = AOP_EDEVICE;
+        if (rc == AOP_OK && h_bnd &&
+            hipMemcpy(h_bnd, db, sizeof(int64_t) * (size_t)stride, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = AOP_EDEVICE;
+        if (rc == AOP_OK && ost != AOP_OK) rc = (aop_status)ost;
+    }
+    if (ws) (void)hipFree(ws);
+    if (dp) (void)hipFree(dp);
+    if (db) (void)hipFree(db);
+    return rc;
+}
+
+aop_status aop_sync(void *stream)
+{
+    return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? AOP_OK : AOP_EDEVICE;
+}
+
+}  // extern "C"

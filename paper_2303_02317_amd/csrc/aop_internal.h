@@ -1,0 +1,49 @@
+// aop_internal.h -- descriptor layout shared by the host API and the gfx950
+// kernels of libaop (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+
+namespace aop {
+
+enum Model : int32_t { BINOMIAL = 0, TRINOMIAL = 1, BSM = 2 };
+
+// Sentinel of "no exercise cell" for the BSM boundary output.
+constexpr int64_t BSM_NONE = INT64_MIN;
+
+// Error codes an option's kernel can record (in Desc::dev_err) when one of
+// its internal geometry checks fails; the option's price is then NaN.
+enum DevErr : int32_t { DEV_OK = 0, DEV_RANGE = 1, DEV_STACK = 2, DEV_ARENA = 3, DEV_FFT = 4 };
+
+// Per-option descriptor, built on the host from the paper's formulas and
+// copied to the device (128 bytes).
+struct Desc {
+    int32_t model;   // Model
+    int32_t prec;    // 0 FP64, 1 mixed
+    int64_t T;       // time steps
+    double S, K;     // spot, strike
+    double a;        // exercise exponent step: binomial a = V sqrt(dt) (S e^{(2j-i)a}),
+                     // trinomial A = V sqrt(2 dt) (S e^{(j-i)A}), BSM ds (1 - e^{s0 + k ds})
+    double s0;       // BSM: ln(S/K); 0 otherwise
+    double w0, w1, w2;  // one-step stencil: binomial (w_dn on j, w_up on j+1, 0);
+                        // trinomial (m p_d on j, m p_o on j+1, m p_u on j+2);
+                        // BSM (b on k-1, c on k, a on k+1)
+    int64_t ws_off;     // byte offset of this option's area in the workspace
+    int64_t row_len;    // doubles per row buffer
+    int64_t arena_len;  // doubles in the recursion arena
+    int64_t nfft;       // complex elements in the FFT scratch
+    int64_t out_index;  // index of this option in the caller's arrays
+    int64_t no_green;   // lattice call with Y = 0: no exercise cell below the expiry row (Lemma 2.3)
+    int64_t reserved;
+};
+static_assert(sizeof(Desc) == 128, "descriptor is 128 bytes");
+
+constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22
+constexpr int64_t TW_N = int64_t(1) << LG_TW;
+
+// Host-side launchers (defined in aop_solver.hip / aop_plain.hip).
+int launch_twiddles(void *d_tw, void *stream);
+int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price,
+                 int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, void *stream);
+int launch_plain(const Desc *d_desc, int64_t n, char *d_ws, double *d_price, void *stream);
+
+}  // namespace aop

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Prices must agree within the FP64 tolerance of ``tests/parity.py``; boundaries
+must agree exactly except where the oracle's own decision is a near-tie.
+Every input is seeded (``paper_2303_02317_amd.inputs``).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2303_02317_amd import inputs
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_02317_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, opts, boundary=True):
+    from paper_2303_02317_amd import binding
+
+    say("gpu batch:", len(opts), "options, models", sorted({o["model"] for o in opts}),
+        "T in", sorted({o["T"] for o in opts})[:6])
+    return binding.price_batch(ctx, opts, boundary=boundary)
+
+
+def check_against_oracle(oracle_mod, opts, prices, status, bnds, check_boundary=True):
+    refs = oracle_mod.price_many(opts, boundary=True, margin=True)
+    fails = []
+    for k, (o, (ref, ob, mg)) in enumerate(zip(opts, refs)):
+        assert status[k] == 0, (o, status[k])
+        if not parity.price_ok(prices[k], ref, o["K"]):
+            fails.append(("price", o, prices[k], ref, parity.price_errors(prices[k], ref)))
+        if check_boundary and bnds is not None:
+            bad = parity.boundary_mismatches(bnds[k][:o["T"] + 1], ob, mg, o["model"], o["T"])
+            if bad:
+                fails.append(("boundary", o, bad[:5], len(bad)))
+    assert not fails, fails[:4]
+
+
+SMALL_T = [1, 2, 3, 5, 31, 63, 64, 65, 66, 100, 129, 257, 1000, 2047, 2049, 4100]
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_small_T_parity(ctx, oracle_mod, model):
+    opts = []
+    for T in SMALL_T:
+        opts += inputs.batch(700 + model, T % 64, 3, model, T=T)
+    p, s, b = run(ctx, opts)
+    check_against_oracle(oracle_mod, opts, p, s, b)
+
+
+EDGE = [
+    (100.0, 100.0, 0.05, 0.03, 0.2, 1.0),    # config 1 point (tie at expiry)
+    (150.0, 50.0, 0.01, 0.06, 0.1, 2.0),     # deep ITM: immediate exercise
+    (50.0, 150.0, 0.08, 0.01, 0.5, 0.25),    # deep OTM: tiny price
+    (100.0, 100.0, 0.08, 0.06, 0.5, 2.0),
+    (60.0, 140.0, 0.01, 0.06, 0.1, 0.25),
+    (100.0, 101.0, 0.001, 0.08, 0.15, 1.5),  # q > r
+    (100.0, 100.0, 0.05, 1e-4, 0.2, 1.0),    # tiny dividend: wide continuation region
+]
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_edge_parameters(ctx, oracle_mod, model):
+    opts = []
+    for (S, K, r, q, s, E) in EDGE:
+        for T in (63, 64, 66, 127, 129, 1000, 4096):
+            opts.append(inputs.option(model, S, K, r, 0.0 if model == 2 else q, s, E, T))
+    p, st, b = run(ctx, opts)
+    check_against_oracle(oracle_mod, opts, p, st, b)
+
+
+def test_no_dividend_call_is_european(ctx, oracle_mod):
+    # Y = 0: the whole lattice is continuation (Lemma 2.3); the price must match
+    # the oracle (and its European value) even when lattice values span e^40.
+    opts = [inputs.option(m, 140.0, 60.0, 0.08, 0.0, 0.3, 1.0, T) for m in (0, 1) for T in (50, 1000, 4096, 10000)]
+    p, st, _ = run(ctx, opts, boundary=False)
+    for k, o in enumerate(opts):
+        ref = oracle_mod.price_option(o)
+        eu = oracle_mod.price_option(o, american=False)
+        assert abs(ref - eu) <= 1e-12 * ref
+        assert parity.price_ok(p[k], ref, o["K"]), (o, p[k], ref)
+
+
+def test_invalid_options_do_not_poison_batch(ctx, oracle_mod):
+    good = inputs.batch(710, 8, 4, 0, T=300)
+    bad = [dict(good[0], S0=-5.0), dict(good[0], model=2), dict(good[0], T=0)]
+    opts = [good[0], bad[0], good[1], bad[1], good[2], bad[2], good[3]]
+    p, st, _ = run(ctx, opts, boundary=False)
+    assert list(st) == [0, 1, 0, 1, 0, 1, 0]
+    for k in (1, 3, 5):
+        assert np.isnan(p[k])
+    for k, o in ((0, good[0]), (2, good[1]), (4, good[2]), (6, good[3])):
+        assert parity.price_ok(p[k], oracle_mod.price_option(o), o["K"])
+
+
+def test_alone_equals_in_batch(ctx):
+    # Each option's schedule depends only on the option, so its result is
+    # bitwise the same alone and inside a mixed batch.
+    mix = []
+    for m in (0, 1, 2):
+        mix += inputs.batch(720 + m, 10, 3, m, T=700 + 300 * m)
+    pb, _, bb = run(ctx, mix)
+    for k, o in enumerate(mix):
+        pa, _, ba = run(ctx, [o])
+        assert pa[0] == pb[k]
+        assert np.array_equal(ba[0][:o["T"] + 1], bb[k][:o["T"] + 1])
+
+
+def test_synchronous_entry_point(ctx, oracle_mod):
+    from paper_2303_02317_amd import binding
+
+    o = dict(inputs.CONFIG1)
+    say("aop_price config 1")
+    p, b = binding.price_one(ctx, o, boundary=True)
+    ref, ob, mg = oracle_mod.price_option(o, boundary=True, margin=True)
+    assert parity.price_ok(p, ref, o["K"])
+    assert not parity.boundary_mismatches(b, ob, mg, 0, o["T"])
+
+
+GOLDEN = sorted(f for f in os.listdir(os.path.join(HERE, "golden")) if f.startswith("oracle_") and f.endswith(".json"))
+
+
+@pytest.mark.parametrize("fname", GOLDEN)
+def test_golden_full_size(ctx, fname):
+    # Benchmark-size workloads against oracle values written by
+    # tests/golden/make_golden.py (which calls only the oracle).
+    doc = json.load(open(os.path.join(HERE, "golden", fname)))
+    recs = doc["options"]
+    opts = [r["params"] for r in recs]
+    p, st, b = run(ctx, opts)
+    fails = []
+    for k, r in enumerate(recs):
+        o = r["params"]
+        if not parity.price_ok(p[k], r["price"], o["K"]):
+            fails.append(("price", k, p[k], r["price"], parity.price_errors(p[k], r["price"])))
+        rows = np.asarray(r["boundary_rows"])
+        diff = np.abs(b[k][rows] - np.asarray(r["boundary"]))
+        if o["model"] == 2:
+            ok = (b[k][rows] == np.asarray(r["boundary"])) | (diff <= 1)
+        else:
+            ok = diff <= 1
+        if not ok.all():
+            fails.append(("boundary", k, rows[~ok][:5]))
+    say(fname, "max rel err", max(parity.price_errors(p[k], r["price"])[1] for k, r in enumerate(recs)))
+    assert not fails, fails[:4]
