@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT nonlinear-stencil American option pricer on one MI355X.
+
+A step prices one batch of seeded synthetic options (default: 64 binomial
+American calls at T = 2^20, the large size of the binomial FFT-vs-plain
+workload) through the C ABI.  Prints one JSON line:
+
+  value        whole-job equivalent lattice cells per second, sum(T^2) / time
+  roofline     the solver kernel's algorithmic HBM bytes per launch (sum over
+               FFT correlations of 8 (n_in + n_out) bytes, plus the directly
+               computed expiry-adjacent row) over its average launch time,
+               against the 8 TB/s HBM3E peak; band_fp64 gives the band
+               stencil's FP64 rate against the 78.6 TFLOP/s vector peak
+  accuracy     max error against stored oracle prices of the same options
+  cpu_baseline the CPU oracle (plain Theta(T^2) induction) on a bounded
+               sample, one option per host thread
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2T 20]
+                       [--options 64] [--option-type binomial|trinomial|bsm]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "equiv. lattice cells/s (T^2/t) at ≤1e-6 rel err vs FP64; serve p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VEC_PEAK_TFLOPS = 78.6
+TYPES = {"binomial": 0, "trinomial": 1, "bsm": 2}
+CONFIG_ID = {0: 2, 1: 3, 2: 4}  # seeded workload ids of the three option types
+GOLDEN_NAME = {0: "binomial", 1: "trinomial", 2: "bsm"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def golden_prices(model: int, log2T: int):
+    path = os.path.join(ROOT, "tests", "golden",
+                        "oracle_%s_c%d_t%d.json" % (GOLDEN_NAME[model], CONFIG_ID[model], log2T))
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    return [r["price"] for r in doc["options"]]
+
+
+def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
+    """Time the CPU oracle on a bounded sample of the workload's option batch."""
+    import oracle
+    from paper_2303_02317_amd import inputs
+
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    # Sample: the first options of the same seeded batch, at a T whose Theta(T^2)
+    # oracle cost per option is a few seconds (the oracle's T^2/s rate does not
+    # depend on T); 2 options per thread.
+    sT = min(log2T, 17 if model == 0 else 16)
+    sample = inputs.batch(CONFIG_ID[model], sT, 2 * cores, model)
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.price_many(sample, threads=cores)
+    dt = time.perf_counter() - t0
+    cells = sum(float(o["T"]) ** 2 for o in sample)
+    return {"value": cells / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": "first %d options of the same seeded batch (config id %d) at T=2^%d, one option per "
+                      "thread, plain FP64 backward induction" % (len(sample), CONFIG_ID[model], sT)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--log2T", type=int, default=20)
+    ap.add_argument("--options", type=int, default=64)
+    ap.add_argument("--option-type", choices=sorted(TYPES), default="binomial")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the pricer shards by option across GPUs with no collectives, "
+              "and this build measures the one-GPU share (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2303_02317_amd import binding, inputs
+
+    model = TYPES[args.option_type]
+    opts = inputs.batch(CONFIG_ID[model], args.log2T, args.options, model)
+    n = len(opts)
+    cells = sum(float(o["T"]) ** 2 for o in opts)
+    log("bench: %s, T=2^%d, %d options, steps=%d warmup=%d" % (args.option_type, args.log2T, n, args.steps,
+                                                               args.warmup))
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(binding.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
+    L = None
+    for w in range(args.warmup):
+        L = binding.launch_batch(ctx, opts, workspace=ws)
+        torch.cuda.synchronize()
+        log("warmup step %d done" % w)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        L = binding.launch_batch(ctx, opts, workspace=ws)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    log("timed %d steps: %.3f s wall, launches %s ms" % (args.steps, wall, ["%.2f" % x for x in launch_ms]))
+
+    prices = L.price.cpu().numpy()
+    status = L.status
+    st = binding.batch_stats(L, n)
+    F = {f: i for i, f in enumerate(binding.STATS_FIELDS)}
+    alg_bytes = 8.0 * float(st[:, F["conv_in"]].sum() + st[:, F["conv_out"]].sum() + st[:, F["direct_cells"]].sum())
+    band_rows = float(st[:, F["band_rows"]].sum())
+    band_flops = band_rows * 64 * (3.0 if model == 0 else 5.0)  # per lane: 1 mul + 1 fma (+1 fma trinomial/BSM)
+    avg_s = float(np.mean(launch_ms)) / 1e3
+    achieved = alg_bytes / avg_s / 1e9
+
+    ref = golden_prices(model, args.log2T)
+    accuracy = None
+    if ref is not None:
+        # Relative error is reported for prices >= 1e-3 K; below that the FFT's
+        # normwise error makes it meaningless, and the absolute error in units
+        # of K is reported instead (tolerances 1e-9 relative / 1e-13 K for FP64).
+        k = min(len(ref), n)
+        big = [i for i in range(k) if abs(ref[i]) >= 1e-3 * opts[i]["K"]]
+        small = [i for i in range(k) if abs(ref[i]) < 1e-3 * opts[i]["K"]]
+        rel = [abs(prices[i] - ref[i]) / abs(ref[i]) for i in big]
+        ab = [abs(prices[i] - ref[i]) / opts[i]["K"] for i in small]
+        within = all(r <= 1e-9 for r in rel) and all(a <= 1e-13 for a in ab)
+        accuracy = {"n_checked": k, "n_rel": len(big), "max_rel_err": max(rel) if rel else None,
+                    "n_small": len(small), "max_abs_err_over_K_small": max(ab) if ab else None,
+                    "within_fp64_tolerance": within,
+                    "reference": "CPU oracle (FP64 plain induction), stored"}
+    ok = bool(np.all(status == 0) and np.all(np.isfinite(prices)))
+
+    line = {
+        "metric": METRIC,
+        "value": cells * args.steps / wall,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s American %s, FFT nonlinear stencil, T=2^%d, %d seeded options"
+                               % (args.option_type, "put" if model == 2 else "call", args.log2T, n),
+                   "option_type": args.option_type, "T": 1 << args.log2T, "options": n,
+                   "seed": [CONFIG_ID[model], args.log2T], "precision": "fp64", "gpus": 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "solve_kernel",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_s * 1e3},
+        "band_fp64": {"achieved": band_flops / avg_s / 1e12, "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": band_flops / avg_s / 1e12 / FP64_VEC_PEAK_TFLOPS, "band_rows_per_launch": band_rows},
+        "work": {f: int(st[:, i].sum()) for f, i in F.items() if f not in ("max_depth",)},
+        "accuracy": accuracy,
+        "all_ok": ok,
+    }
+    line["work"]["max_depth"] = int(st[:, F["max_depth"]].max())
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline(opts, model, args.log2T)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,23 @@ aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *h_opts, int64_t
                                  void *d_workspace, size_t ws_bytes, double *d_price,
                                  int32_t *h_status, void *hip_stream);
 
+/* Work an option's solve performed (written by the kernel into the workspace). */
+typedef struct {
+    int64_t convs;        /* FFT correlations (h-step kernel applications) */
+    int64_t conv_in;      /* sum of input lengths (doubles read from HBM) */
+    int64_t conv_out;     /* sum of output lengths (doubles written to HBM) */
+    int64_t fft_points;   /* sum of transform sizes N */
+    int64_t band_rows;    /* row steps of the band stencil (the span) */
+    int64_t direct_cells; /* cells of the expiry-adjacent row computed directly */
+    int64_t max_depth;    /* deepest trapezoid recursion level */
+    int64_t trapezoids;   /* top-level trapezoids */
+} aop_stats;
+
+/* Copy the work counters of the last aop_price_batch on this workspace to the
+ * host (synchronous; call after the stream has passed the batch).  h_stats:
+ * n entries; entries of rejected options are zero. */
+aop_status aop_batch_stats(const void *d_workspace, int64_t n, aop_stats *h_stats);
+
 /* Synchronous convenience: price one option, allocating and freeing its own
  * workspace.  h_boundary: NULL or a host array of T+1 int64. */
 aop_status aop_price(aop_ctx *ctx, const aop_option *h_opt, int32_t precision, double *h_price,

@@ -24,8 +24,11 @@ BSM_NONE = np.iinfo(np.int64).min
 
 #: Every symbol include/aop.h declares.
 EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
-           "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_price", "aop_sync", "aop_status_str",
-           "aop_version"]
+           "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
+           "aop_status_str", "aop_version"]
+
+STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
+                "trapezoids"]
 
 
 class AopError(RuntimeError):
@@ -58,6 +61,7 @@ def load():
         "aop_price_batch": (I32, [P, P, I64, I32, P, SZ, P, P, P, I64, P]),
         "aop_plain_workspace_bytes": (I32, [P, I64, ctypes.POINTER(SZ)]),
         "aop_price_batch_plain": (I32, [P, P, I64, P, SZ, P, P, P]),
+        "aop_batch_stats": (I32, [P, I64, P]),
         "aop_price": (I32, [P, P, I32, ctypes.POINTER(D), P]),
         "aop_sync": (I32, [P]),
         "aop_status_str": (ctypes.c_char_p, [I32]),
@@ -197,6 +201,14 @@ def launch_plain(ctx: Context, opts, stream=None, workspace=None):
                                    _stream_handle(stream))
     _check(rc, "aop_price_batch_plain")
     return Launch(price[:n], status[:n], None, workspace)
+
+
+def batch_stats(launch: "Launch", n: int) -> np.ndarray:
+    """Work counters of a finished launch: int64 array [n, len(STATS_FIELDS)]."""
+    out = np.zeros((max(n, 1), len(STATS_FIELDS)), dtype=np.int64)
+    _check(load().aop_batch_stats(ctypes.c_void_p(launch.workspace.data_ptr()), n,
+                                  out.ctypes.data_as(ctypes.c_void_p)), "aop_batch_stats")
+    return out[:n]
 
 
 def price_one(ctx: Context, opt, precision: int = AOP_FP64, boundary: bool = False):

@@ -146,7 +146,7 @@ size_t option_bytes(const Desc &d)
 // Build descriptors for a batch; returns total workspace bytes.
 size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambda, Desc *out, int32_t *status)
 {
-    size_t off = align_up(sizeof(Desc) * (size_t)std::max<int64_t>(n, 1));
+    size_t off = (size_t)aop::stats_offset(n) + align_up(sizeof(aop::Stats) * (size_t)std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; ++i) {
         Desc &d = out[i];
         aop_status st = make_desc(opts[i], lambda, d);
@@ -340,6 +340,17 @@ aop_status aop_price(aop_ctx *ctx, const aop_option *opt, int32_t precision, dou
     if (dp) (void)hipFree(dp);
     if (db) (void)hipFree(db);
     return rc;
+}
+
+aop_status aop_batch_stats(const void *d_ws, int64_t n, aop_stats *h_stats)
+{
+    static_assert(sizeof(aop_stats) == sizeof(aop::Stats), "stats layout");
+    if (!d_ws || !h_stats || n < 0) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    const char *src = (const char *)d_ws + aop::stats_offset(n);
+    return hipMemcpy(h_stats, src, sizeof(aop_stats) * (size_t)n, hipMemcpyDeviceToHost) == hipSuccess
+               ? AOP_OK
+               : AOP_EDEVICE;
 }
 
 aop_status aop_sync(void *stream)

@@ -275,6 +275,17 @@ __device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll 
     }
 }
 
+__device__ __forceinline__ void count_conv(Stats *st, ll n_in, ll n_out)
+{
+    if (threadIdx.x == 0 && st && n_out > 0) {
+        int l = ceil_log2(n_in);
+        st->convs += 1;
+        st->conv_in += n_in;
+        st->conv_out += n_out;
+        st->fft_points += ll(1) << (l < 1 ? 1 : l);
+    }
+}
+
 // ------------------------------------------------------------ band walkers
 // Executed by the 64 lanes of wave 0.  Lane l holds one cell of the current
 // row; the neighbour a row step needs comes from the next lane, and cells
@@ -416,6 +427,7 @@ struct Frame {
 
 struct Ctx {
     const Desc *d;
+    Stats *st;  // work counters in LDS (updated by lane 0 only)
     double *lo, *hi;  // this option's workspace (doubles) for range checks
     double *arena;
     ll arena_len;
@@ -470,7 +482,10 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                             const ll r = (d.model == BINOMIAL)
                                              ? band_bin(d, i0, c0, h, b, fr.src, fr.dst, cx.bnd, nullptr)
                                              : band_tri(d, i0, c0, h, b, fr.src, fr.dst, cx.bnd, nullptr);
-                            if (tid == 0) *leaf_sh = r;
+                            if (tid == 0) {
+                                *leaf_sh = r;
+                                cx.st->band_rows += h;
+                            }
                         }
                         __syncthreads();
                         result = *leaf_sh;
@@ -482,6 +497,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     if (fr.aoff + nred > cx.arena_len) e = DEV_ARENA;
                     else if (!in_ws(cx, fr.src, c0, b)) e = DEV_RANGE;
                     else {
+                        count_conv(cx.st, nred, nred - span * h1);
                         fft_correlate(d, fr.src + c0, nred, h1, (span == 1) ? 0 : h1, nred - span * h1,
                                       mid + c0, cx.scr, cx.lds, cx.tw);
                         fr.mid = mid;
@@ -496,6 +512,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                 const ll n2 = br - c0 + 1;
                 if (!in_ws(cx, fr.mid, c0, br) || !in_ws(cx, fr.dst, c0, br)) e = DEV_RANGE;
                 else {
+                    count_conv(cx.st, n2, n2 - span * h2);
                     if (n2 - span * h2 > 0)
                         fft_correlate(d, fr.mid + c0, n2, h2, (span == 1) ? 0 : h2, n2 - span * h2,
                                       fr.dst + c0, cx.scr, cx.lds, cx.tw);
@@ -522,7 +539,10 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     } else {
                         if (tid < 64) {
                             const ll r = band_bsm(d, n, f, h, f + 2 * h, fr.src, fr.dst, cx.bnd, nullptr);
-                            if (tid == 0) *leaf_sh = r;
+                            if (tid == 0) {
+                                *leaf_sh = r;
+                                cx.st->band_rows += h;
+                            }
                         }
                         __syncthreads();
                         result = *leaf_sh;
@@ -536,6 +556,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     else if (!in_ws(cx, fr.src, f + 1, f + 2 * h)) e = DEV_RANGE;
                     else {
                         // conv 1: red cells [f+1, f+2h] -> [f+1+h1, f+2h-h1] of step n+h1
+                        count_conv(cx.st, 2 * h, 2 * h - 2 * h1);
                         fft_correlate(d, fr.src + f + 1, 2 * h, h1, h1, 2 * h - 2 * h1, mid + f + 1 + h1,
                                       cx.scr, cx.lds, cx.tw);
                         fr.mid = mid;
@@ -550,6 +571,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                 else if (!in_ws(cx, fr.mid, fp + 1, f + h + h2) || !in_ws(cx, fr.dst, fp + 1 + h2, f + h)) e = DEV_RANGE;
                 else {
                     // conv 2: red cells [f'+1, f+h+h2] of step n+h1 -> [f'+1+h2, f+h] of step n+h
+                    count_conv(cx.st, nin, nin - 2 * h2);
                     fft_correlate(d, fr.mid + fp + 1, nin, h2, h2, nin - 2 * h2, fr.dst + fp + 1 + h2,
                                   cx.scr, cx.lds, cx.tw);
                     fr.ret1 = fp;
@@ -573,6 +595,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                 stk[s] = fr;
                 stk[s + 1] = child;
                 *sp_sh = s + 1;
+                if (s + 1 > cx.st->max_depth) cx.st->max_depth = s + 1;
             }
         }
         __syncthreads();
@@ -614,6 +637,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
             if (red) lastT1 = j;
         }
     }
+    if (tid == 0) cx.st->direct_cells += wT + 1 - (bin ? 1 : 2);
     lastT = block_max(lastT, red_sh);
     lastT1 = block_max(lastT1, red_sh);
     if (cx.bnd && tid == 0) {
@@ -640,6 +664,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
         if (cx.bnd)
             for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = bin ? i : 2 * i;
         const ll hh = T - 1;
+        count_conv(cx.st, b + 1, 1);
         fft_correlate(d, src, b + 1, hh, bin ? 0 : hh, 1, val_sh, cx.scr, cx.lds, cx.tw, beta, tc);
         __syncthreads();
         return *val_sh;
@@ -653,6 +678,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
         }
         const ll nred = b + 1;
         if (nred <= BAND) {  // the band walks the leftover triangle to the root
+            if (tid == 0) cx.st->band_rows += i0;
             if (tid < 64) {
                 if (bin) band_bin(d, i0, 0, i0, b, src, dst, cx.bnd, val_sh);
                 else band_tri(d, i0, 0, i0, b, src, dst, cx.bnd, val_sh);
@@ -663,6 +689,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
         ll h = bin ? nred : nred / 2;
         if (h > i0) h = i0;
         Frame root{i0, 0, h, b, 0, 0, src, dst, nullptr, 0, 0};
+        if (tid == 0) cx.st->trapezoids += 1;
         b = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, err_sh, leaf_sh);
         if (*err_sh) return NAN;
         i0 -= h;
@@ -697,6 +724,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
             if (green) f1 = k;
         }
     }
+    if (tid == 0) cx.st->direct_cells += 2 * T - 1;
     f0 = block_max(f0, red_sh);
     f1 = block_max(f1, red_sh);
     if (cx.bnd && tid == 0) {
@@ -716,6 +744,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
             if (cx.bnd)
                 for (ll m = n + 1 + tid; m <= T; m += WG) cx.bnd[m] = NONE;
             const ll hh = T - n;
+            count_conv(cx.st, R - L + 1, 1);
             fft_correlate(d, src + L, R - L + 1, hh, hh, 1, val_sh, cx.scr, cx.lds, cx.tw);
             __syncthreads();
             return d.K * (*val_sh);
@@ -728,6 +757,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
         }
         const ll w = R - f;
         if (w <= BAND - 2) {  // the band walks the leftover cone to the apex
+            if (tid == 0) cx.st->band_rows += T - n;
             if (tid < 64) band_bsm(d, n, f, T - n, R, src, dst, cx.bnd, val_sh);
             __syncthreads();
             return d.K * (*val_sh);
@@ -735,9 +765,11 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
         ll h = w / 2;
         if (h > T - n) h = T - n;
         Frame root{n, f, h, 0, 0, 0, src, dst, nullptr, 0, 0};
+        if (tid == 0) cx.st->trapezoids += 1;
         const ll fn = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, err_sh, leaf_sh);
         if (*err_sh) return NAN;
         // the rest of step n+h: red cells [f+1+h, R-h] from [f+1, R] of step n
+        count_conv(cx.st, w, w - 2 * h);
         fft_correlate(d, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h, cx.scr, cx.lds, cx.tw);
         n += h;
         R -= h;
@@ -751,17 +783,21 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
 
 __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ descs, char *ws,
                                                    const double2 *__restrict__ tw, double *price,
-                                                   ll *bnd, ll bnd_stride, int32_t *err)
+                                                   ll *bnd, ll bnd_stride, int32_t *err, Stats *stats)
 {
     __shared__ double2 lds[NLDS];
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
     __shared__ ll ret_sh, leaf_sh, red_sh[WG / 64];
     __shared__ double val_sh;
+    __shared__ Stats st_sh;
 
     const Desc d = descs[blockIdx.x];
     if (d.model < 0) {  // rejected on the host: no work, price NaN
-        if (threadIdx.x == 0) price[d.out_index] = NAN;
+        if (threadIdx.x == 0) {
+            price[d.out_index] = NAN;
+            stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0};
+        }
         return;
     }
     char *base = ws + d.ws_off;
@@ -779,9 +815,11 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     cx.lds = lds;
     cx.tw = tw;
     cx.bnd = bnd ? bnd + d.out_index * bnd_stride : nullptr;
+    cx.st = &st_sh;
     if (threadIdx.x == 0) {
         err_sh = 0;
         ret_sh = 0;
+        st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0};
     }
     __syncthreads();
     double p;
@@ -793,6 +831,7 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     if (threadIdx.x == 0) {
         price[d.out_index] = err_sh ? NAN : p;
         if (err) err[d.out_index] = err_sh;
+        stats[d.out_index] = st_sh;
     }
 }
 
@@ -818,7 +857,8 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(solve_kernel, dim3((unsigned)n), dim3(WG), 0, (hipStream_t)stream, d_desc, d_ws,
-                       (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err);
+                       (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err,
+                       (Stats *)(d_ws + stats_offset(n)));
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
