@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--options", type=int, default=64)
     ap.add_argument("--option-type", choices=sorted(TYPES), default="binomial")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain", action="store_true",
+                    help="also time the plain Theta(T^2) GPU stencil on the same batch (one step)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -174,6 +176,21 @@ def main():
         "all_ok": ok,
     }
     line["work"]["max_depth"] = int(st[:, F["max_depth"]].max())
+    if args.plain:
+        log("plain O(T^2) GPU stencil on the same batch ...")
+        wsp = torch.empty(binding.plain_workspace_bytes(opts), dtype=torch.uint8, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0.record(stream)
+        P = binding.launch_plain(ctx, opts, workspace=wsp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t1
+        pp = P.price.cpu().numpy()
+        agree = float(np.max(np.abs(pp - prices) / np.maximum(np.abs(pp), 1e-3 * np.array([o["K"] for o in opts]))))
+        line["plain_gpu"] = {"value": cells / pw, "unit": "cells/s", "ms": pw * 1e3, "event_ms": e0.elapsed_time(e1),
+                             "speedup_fft_vs_plain": pw / (wall / args.steps), "max_rel_diff_vs_fft": agree}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(opts, model, args.log2T)

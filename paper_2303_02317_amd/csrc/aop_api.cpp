@@ -165,6 +165,26 @@ size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambd
     return off;
 }
 
+// Descriptors for the plain stencil: two row buffers per option.
+size_t build_plain(const aop_option *opts, int64_t n, double lambda, Desc *out, int32_t *status)
+{
+    size_t off = align_up(sizeof(Desc) * (size_t)std::max<int64_t>(n, 1));
+    for (int64_t i = 0; i < n; ++i) {
+        Desc &d = out[i];
+        aop_status st = make_desc(opts[i], lambda, d);
+        d.out_index = i;
+        if (status) status[i] = st;
+        if (st != AOP_OK) {
+            d.model = -1;
+            continue;
+        }
+        geometry(d);
+        d.ws_off = (int64_t)off;
+        off += align_up(sizeof(double) * 2 * (size_t)d.row_len);
+    }
+    return off;
+}
+
 aop_status ensure_stage(aop_ctx *ctx, size_t n)
 {
     if (ctx->stage_pending) {
@@ -290,17 +310,32 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
 
 aop_status aop_plain_workspace_bytes(const aop_option *opts, int64_t n, size_t *bytes)
 {
-    (void)opts;
-    (void)n;
-    if (bytes) *bytes = 0;
-    return AOP_ENOTIMPL;
+    if (!bytes || n < 0 || (n > 0 && !opts)) return AOP_EINVAL;
+    std::vector<Desc> d((size_t)std::max<int64_t>(n, 1));
+    *bytes = build_plain(opts, n, 1.0 / 3.0, d.data(), nullptr);
+    return AOP_OK;
 }
 
 aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *opts, int64_t n, void *d_ws,
                                  size_t ws_bytes, double *d_price, int32_t *h_status, void *stream)
 {
-    (void)ctx; (void)opts; (void)n; (void)d_ws; (void)ws_bytes; (void)d_price; (void)h_status; (void)stream;
-    return AOP_ENOTIMPL;
+    if (!ctx || n < 0 || (n > 0 && (!opts || !d_ws || !d_price))) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    aop_status st = ensure_stage(ctx, (size_t)n);
+    if (st != AOP_OK) return st;
+    std::vector<int32_t> stat((size_t)n);
+    const size_t need = build_plain(opts, n, ctx->lambda, ctx->h_stage, stat.data());
+    if (h_status) std::memcpy(h_status, stat.data(), sizeof(int32_t) * (size_t)n);
+    if (ws_bytes < need) return AOP_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(d_ws, ctx->h_stage, sizeof(Desc) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AOP_EDEVICE;
+    if (aop::launch_plain_batch((const Desc *)d_ws, ctx->h_stage, n, (char *)d_ws, d_price, stream) != 0)
+        return AOP_EDEVICE;
+    if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
+    ctx->stage_pending = true;
+    return AOP_OK;
 }
 
 aop_status aop_price(aop_ctx *ctx, const aop_option *opt, int32_t precision, double *h_price,

@@ -1,0 +1,180 @@
+// aop_plain.hip -- the plain Theta(T^2) backward induction of Fig. 1 on gfx950,
+// batched over options: the comparison path for the FFT method.
+//
+// Every cell of the lattice / grid is updated with the direct
+// max(continuation, exercise) stencil, in FP64, with the tie rule of
+// Definition 2.1.  Temporal tiling: one launch advances every option by R
+// rows; each wave64 holds a tile of 64*C consecutive cells in registers
+// (C per lane), takes the R row steps with neighbour values exchanged by
+// wave shuffles, and writes back the cells whose dependency cone stayed inside
+// the tile (R*span cells of halo are recomputed by the neighbouring tile).
+// Exercise values are carried per cell by one multiplication per row and
+// re-seeded with exp() at every launch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "aop_internal.h"
+
+namespace aop {
+
+typedef long long ll;
+
+#define PL_C 16                    // cells per lane
+#define PL_W (64 * PL_C)           // cells per wave tile
+#define PL_R 64                    // rows per launch
+#define PL_WAVES 4                 // waves (tiles) per workgroup
+
+__device__ __forceinline__ bool pl_red(double c, double e)
+{
+    return (c >= e) && (c < INFINITY) && (e < INFINITY);
+}
+
+// One launch: option blockIdx.y, tiles blockIdx.x * PL_WAVES + wave.
+// Lattices: rows itop -> itop - r (r = min(R, itop)), itop = T - L*R, the
+// input row of the first launch (row T) evaluated in closed form.
+// BSM: steps n -> n + r, n = L*R, r = min(R, T - n), step 0 in closed form.
+__global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__restrict__ descs, char *ws,
+                                                              double *price, ll L)
+{
+    const Desc d = descs[blockIdx.y];
+    if (d.model < 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && L == 0) price[d.out_index] = NAN;
+        return;
+    }
+    const ll T = d.T;
+    const int lane = threadIdx.x & 63;
+    const ll tile = (ll)blockIdx.x * PL_WAVES + (threadIdx.x >> 6);
+    double *rowA = (double *)(ws + d.ws_off);
+    double *rowB = rowA + d.row_len;
+    double *in = (L & 1) ? rowB : rowA;
+    double *out = (L & 1) ? rowA : rowB;
+    double g[PL_C], x[PL_C];
+
+    if (d.model != BSM) {
+        const bool bin = d.model == BINOMIAL;
+        const int span = bin ? 1 : 2;
+        const ll itop = T - L * PL_R;
+        if (itop <= 0) return;
+        const ll r = itop < PL_R ? itop : PL_R;
+        const ll wout = PL_W - span * r;           // valid cells per tile
+        const ll ilast = bin ? itop : 2 * itop;     // last column of row itop
+        const ll j0 = tile * wout;
+        if (j0 > (bin ? itop - r : 2 * (itop - r))) return;
+        const double u = exp(d.a);
+        for (int c = 0; c < PL_C; ++c) {
+            const ll j = j0 + lane * PL_C + c;
+            const double ex = d.S * exp((double)((bin ? 2 * j : j) - itop) * d.a);
+            x[c] = ex;
+            if (L == 0) {
+                const double e = ex - d.K;
+                g[c] = (j <= ilast) ? (pl_red(0.0, e) ? 0.0 : e) : 0.0;
+            } else {
+                g[c] = (j <= ilast) ? in[j] : 0.0;
+            }
+        }
+        for (ll k = 1; k <= r; ++k) {
+            const double n0 = __shfl_down(g[0], 1, 64);
+            const double n1 = __shfl_down(g[1], 1, 64);
+            double nx[PL_C];
+            if (bin) {
+#pragma unroll
+                for (int c = 0; c < PL_C - 1; ++c) nx[c] = d.w0 * g[c] + d.w1 * g[c + 1];
+                nx[PL_C - 1] = d.w0 * g[PL_C - 1] + d.w1 * n0;
+            } else {
+#pragma unroll
+                for (int c = 0; c < PL_C - 2; ++c) nx[c] = d.w0 * g[c] + d.w1 * g[c + 1] + d.w2 * g[c + 2];
+                nx[PL_C - 2] = d.w0 * g[PL_C - 2] + d.w1 * g[PL_C - 1] + d.w2 * n0;
+                nx[PL_C - 1] = d.w0 * g[PL_C - 1] + d.w1 * n0 + d.w2 * n1;
+            }
+#pragma unroll
+            for (int c = 0; c < PL_C; ++c) {
+                x[c] *= u;  // S u^{col - i} one row lower
+                const double e = x[c] - d.K;
+                g[c] = pl_red(nx[c], e) ? nx[c] : e;
+            }
+        }
+        const ll iout = itop - r;
+        const ll olast = bin ? iout : 2 * iout;
+        for (int c = 0; c < PL_C; ++c) {
+            const ll loc = lane * PL_C + c;
+            const ll j = j0 + loc;
+            if (loc < wout && j <= olast) out[j] = g[c];
+        }
+        if (iout == 0 && j0 == 0 && lane == 0) price[d.out_index] = g[0];
+    } else {
+        const ll n = L * PL_R;
+        if (n >= T) return;
+        const ll r = (T - n) < PL_R ? (T - n) : PL_R;
+        const ll wout = PL_W - 2 * r;
+        const ll lo_out = -(T - n - r);            // cone of step n + r
+        const ll k0 = lo_out + tile * wout;        // first output cell of this tile
+        if (k0 > T - n - r) return;
+        const ll kb = k0 - r;                      // first input cell
+        double *A = in + 2 * T + 1, *B = out + 2 * T + 1;
+        for (int c = 0; c < PL_C; ++c) {
+            const ll k = kb + lane * PL_C + c;
+            const double gk = 1.0 - exp(d.s0 + (double)k * d.a);
+            x[c] = gk;
+            const bool incone = (k >= -(T - n)) && (k <= T - n);
+            if (L == 0)
+                g[c] = gk > 0.0 ? gk : 0.0;
+            else
+                g[c] = incone ? A[k] : 0.0;
+        }
+        for (ll k = 1; k <= r; ++k) {
+            const double pv = __shfl_up(g[PL_C - 1], 1, 64);
+            const double nv = __shfl_down(g[0], 1, 64);
+            double nx[PL_C];
+            nx[0] = d.w0 * pv + d.w1 * g[0] + d.w2 * g[1];
+#pragma unroll
+            for (int c = 1; c < PL_C - 1; ++c) nx[c] = d.w0 * g[c - 1] + d.w1 * g[c] + d.w2 * g[c + 1];
+            nx[PL_C - 1] = d.w0 * g[PL_C - 2] + d.w1 * g[PL_C - 1] + d.w2 * nv;
+#pragma unroll
+            for (int c = 0; c < PL_C; ++c) g[c] = (x[c] > nx[c]) ? x[c] : nx[c];
+        }
+        const ll hi_out = T - n - r;
+        for (int c = 0; c < PL_C; ++c) {
+            const ll loc = lane * PL_C + c;
+            const ll k = kb + loc;
+            if (loc >= r && loc < r + wout && k <= hi_out) B[k] = g[c];
+            if (n + r == T && k == 0 && loc >= r && loc < r + wout) price[d.out_index] = d.K * g[c];
+        }
+    }
+}
+
+// Host loop: ceil(Tmax / R) launches; grid.x covers the widest option's tiles.
+int launch_plain_batch(const Desc *d_desc, const Desc *h_desc, int64_t n, char *d_ws, double *d_price,
+                       void *stream)
+{
+    if (n <= 0) return 0;
+    ll Tmax = 0;
+    int span = 1;
+    for (int64_t i = 0; i < n; ++i)
+        if (h_desc[i].model >= 0) {
+            Tmax = h_desc[i].T > Tmax ? h_desc[i].T : Tmax;
+            if (h_desc[i].model != BINOMIAL) span = 2;
+        }
+    const ll launches = Tmax > 0 ? (Tmax + PL_R - 1) / PL_R : 1;
+    for (ll L = 0; L < launches; ++L) {
+        // widest row among options at this launch
+        ll width = 1;
+        for (int64_t i = 0; i < n; ++i) {
+            const Desc &d = h_desc[i];
+            if (d.model < 0) continue;
+            ll w;
+            if (d.model == BSM) w = 2 * (d.T - L * PL_R) + 1;
+            else w = (d.model == BINOMIAL ? 1 : 2) * (d.T - L * PL_R) + 1;
+            width = w > width ? w : width;
+        }
+        const ll wout = PL_W - span * PL_R;
+        const ll tiles = (width + wout - 1) / wout + 1;
+        const unsigned gx = (unsigned)((tiles + PL_WAVES - 1) / PL_WAVES);
+        hipLaunchKernelGGL(plain_kernel, dim3(gx, (unsigned)n), dim3(64 * PL_WAVES), 0, (hipStream_t)stream,
+                           d_desc, d_ws, d_price, L);
+        if (hipGetLastError() != hipSuccess) return 1;
+    }
+    return 0;
+}
+
+}  // namespace aop
