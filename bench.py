@@ -171,11 +171,15 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_s * 1e3},
         "band_fp64": {"achieved": band_flops / avg_s / 1e12, "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": band_flops / avg_s / 1e12 / FP64_VEC_PEAK_TFLOPS, "band_rows_per_launch": band_rows},
-        "work": {f: int(st[:, i].sum()) for f, i in F.items() if f not in ("max_depth",)},
+        "work": {f: int(st[:, i].sum()) for f, i in F.items()
+                 if f not in ("max_depth", "reserved") and not f.startswith("cyc_")},
         "accuracy": accuracy,
         "all_ok": ok,
     }
     line["work"]["max_depth"] = int(st[:, F["max_depth"]].max())
+    tot = float(st[:, F["cyc_total"]].sum()) or 1.0
+    line["phases"] = {k: float(st[:, F["cyc_" + k]].sum()) / tot for k in ("band", "direct", "fft", "rows")}
+    line["phases"]["cycles_per_option"] = tot / max(n, 1)
     if args.plain:
         log("plain O(T^2) GPU stencil on the same batch ...")
         wsp = torch.empty(binding.plain_workspace_bytes(opts), dtype=torch.uint8, device="cuda")

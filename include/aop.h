@@ -143,6 +143,14 @@ typedef struct {
     int64_t direct_cells; /* cells of the expiry-adjacent row computed directly */
     int64_t max_depth;    /* deepest trapezoid recursion level */
     int64_t trapezoids;   /* top-level trapezoids */
+    int64_t n_direct;     /* correlations evaluated by direct stepping */
+    int64_t n_fft;        /* correlations evaluated by FFT */
+    int64_t cyc_band;     /* shader clock cycles spent in the band stencil */
+    int64_t cyc_direct;   /* ... in direct-stepping correlations */
+    int64_t cyc_fft;      /* ... in FFT correlations */
+    int64_t cyc_rows;     /* ... computing the rows next to expiry */
+    int64_t cyc_total;    /* ... in the whole solve */
+    int64_t reserved;
 } aop_stats;
 
 /* Copy the work counters of the last aop_price_batch on this workspace to the

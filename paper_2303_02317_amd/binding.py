@@ -28,7 +28,8 @@ EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_vali
            "aop_status_str", "aop_version"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
-                "trapezoids"]
+                "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_direct", "cyc_fft", "cyc_rows", "cyc_total",
+                "reserved"]
 
 
 class AopError(RuntimeError):

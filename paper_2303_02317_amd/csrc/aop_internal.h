@@ -40,8 +40,9 @@ static_assert(sizeof(Desc) == 128, "descriptor is 128 bytes");
 // Per-option work counters (mirror of aop_stats), stored after the descriptors.
 struct Stats {
     int64_t convs, conv_in, conv_out, fft_points, band_rows, direct_cells, max_depth, trapezoids;
+    int64_t n_direct, n_fft, cyc_band, cyc_direct, cyc_fft, cyc_rows, cyc_total, reserved;
 };
-static_assert(sizeof(Stats) == 64, "stats are 64 bytes");
+static_assert(sizeof(Stats) == 128, "stats are 128 bytes");
 inline int64_t stats_offset(int64_t n) { return ((int64_t)sizeof(Desc) * (n > 0 ? n : 1) + 255) / 256 * 256; }
 
 constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22

@@ -31,6 +31,51 @@ namespace aop {
 
 typedef long long ll;
 
+// Model parameters, passed by value so that they live in registers.
+struct Mp {
+    int model;
+    ll T, no_green;
+    double S, K, a, s0, w0, w1, w2;
+};
+__device__ __forceinline__ Mp make_mp(const Desc &d)
+{
+    Mp p;
+    p.model = d.model;
+    p.T = d.T;
+    p.no_green = d.no_green;
+    p.S = d.S;
+    p.K = d.K;
+    p.a = d.a;
+    p.s0 = d.s0;
+    p.w0 = d.w0;
+    p.w1 = d.w1;
+    p.w2 = d.w2;
+    return p;
+}
+
+// Wave-uniform copy of a value that is uniform by construction.
+__device__ __forceinline__ ll uni(ll v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (ll)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// DPP wave shifts (gfx9 wave_shl1 / wave_shr1): value of lane l+1 (lane 63
+// receives `fill`), value of lane l-1 (lane 0 receives `fill`).  All 64 lanes
+// must be active.
+__device__ __forceinline__ double dpp_dn1(double v, double fill)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double dpp_up1(double v, double fill)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // ------------------------------------------------------------ small helpers
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -52,15 +97,15 @@ __device__ __forceinline__ int ceil_log2(ll n)
 }
 
 // Exercise (green) values, evaluated at need (never stored).
-__device__ __forceinline__ double ex_bin(const Desc &d, ll i, ll j)
+__device__ __forceinline__ double ex_bin(const Mp &d, ll i, ll j)
 {
     return d.S * exp((double)(2 * j - i) * d.a) - d.K;  // S u^{2j-i} - K
 }
-__device__ __forceinline__ double ex_tri(const Desc &d, ll i, ll j)
+__device__ __forceinline__ double ex_tri(const Mp &d, ll i, ll j)
 {
     return d.S * exp((double)(j - i) * d.a) - d.K;  // S u^{j-i} - K
 }
-__device__ __forceinline__ double ex_bsm(const Desc &d, ll k)
+__device__ __forceinline__ double ex_bsm(const Mp &d, ll k)
 {
     return 1.0 - exp(d.s0 + (double)k * d.a);  // 1 - e^{s_k}
 }
@@ -85,89 +130,159 @@ __device__ ll block_max(ll v, ll *sh)
     return r;
 }
 
-// --------------------------------------------------------- LDS radix-2 FFT
-// nb batched transforms of length 2^lg, stored contiguously in LDS.
+// ------------------------------------------------------------ LDS FFT
+// nb batched transforms of length 2^lg <= 2048, stored contiguously in LDS.
 // Forward: decimation in frequency, natural order in -> bit-reversed out.
-__device__ void lds_dif(double2 *x, int lg, int nb, const double2 *__restrict__ tw)
+// Inverse (unnormalised): decimation in time, bit-reversed in -> natural out.
+// Each pass loads 2^K elements per lane, applies K radix-2 stages in
+// registers and stores them back, so a 2048-point transform takes four LDS
+// round trips.  twl holds e^{-2 pi i t / 2048}, t < 1024.
+template <int K, bool INV>
+__device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, const double2 *twl)
 {
-    if (lg <= 0) return;
-    const int n = 1 << lg, half = n >> 1, total = nb * half;
-    for (int s = lg - 1; s >= 0; --s) {
-        const int m = 1 << s;
-        for (int t = threadIdx.x; t < total; t += WG) {
-            const int b = t >> (lg - 1);
-            const int loc = t & (half - 1);
-            const int j = loc & (m - 1);
-            const int a = b * n + ((loc >> s) << (s + 1)) + j;
-            const double2 u = x[a], v = x[a + m];
-            const double2 w = tw[(ll)j << (LG_TW - s - 1)];  // e^{-2 pi i j / 2m}
-            x[a] = make_double2(u.x + v.x, u.y + v.y);
-            x[a + m] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+    constexpr int G = 1 << K;
+    const int n = 1 << lg;
+    const int s_hi = s_lo + K - 1;
+    const int per = n >> K;  // groups per transform
+    const int groups = nb * per;
+    const int jmask = (1 << s_lo) - 1;
+    for (int gi = threadIdx.x; gi < groups; gi += WG) {
+        const int b = gi / per;
+        const int r = gi - b * per;
+        const int j = r & jmask;
+        const int blk = r >> s_lo;
+        const int base = b * n + (blk << (s_hi + 1)) + j;
+        double2 v[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) v[q] = x[base + (q << s_lo)];
+        if (!INV) {
+#pragma unroll
+            for (int t = K - 1; t >= 0; --t) {
+                const int s = s_lo + t;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
+                    const double2 w = twl[jj << (10 - s)];
+                    const double2 u = v[q], z = v[q + (1 << t)];
+                    v[q] = make_double2(u.x + z.x, u.y + z.y);
+                    v[q + (1 << t)] = cmul(make_double2(u.x - z.x, u.y - z.y), w);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const int s = s_lo + t;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
+                    const double2 w = twl[jj << (10 - s)];
+                    const double2 u = v[q], z = cmulc(v[q + (1 << t)], w);
+                    v[q] = make_double2(u.x + z.x, u.y + z.y);
+                    v[q + (1 << t)] = make_double2(u.x - z.x, u.y - z.y);
+                }
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < G; ++q) x[base + (q << s_lo)] = v[q];
+    }
+    __syncthreads();
+}
+
+__device__ void lds_dif(double2 *x, int lg, int nb, const double2 *twl)
+{
+    int s_hi = lg - 1;
+    while (s_hi >= 0) {
+        const int k = s_hi + 1 >= 3 ? 3 : s_hi + 1;
+        const int s_lo = s_hi - k + 1;
+        if (k == 3) lds_pass<3, false>(x, lg, nb, s_lo, twl);
+        else if (k == 2) lds_pass<2, false>(x, lg, nb, s_lo, twl);
+        else lds_pass<1, false>(x, lg, nb, s_lo, twl);
+        s_hi = s_lo - 1;
     }
 }
-// Inverse (unnormalised): decimation in time, bit-reversed in -> natural out.
-__device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *__restrict__ tw)
+
+__device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl)
 {
-    if (lg <= 0) return;
-    const int n = 1 << lg, half = n >> 1, total = nb * half;
-    for (int s = 0; s < lg; ++s) {
-        const int m = 1 << s;
-        for (int t = threadIdx.x; t < total; t += WG) {
-            const int b = t >> (lg - 1);
-            const int loc = t & (half - 1);
-            const int j = loc & (m - 1);
-            const int a = b * n + ((loc >> s) << (s + 1)) + j;
-            const double2 u = x[a];
-            const double2 v = cmulc(x[a + m], tw[(ll)j << (LG_TW - s - 1)]);  // * e^{+2 pi i j / 2m}
-            x[a] = make_double2(u.x + v.x, u.y + v.y);
-            x[a + m] = make_double2(u.x - v.x, u.y - v.y);
-        }
-        __syncthreads();
+    int s_lo = 0;
+    while (s_lo < lg) {
+        const int k = lg - s_lo >= 3 ? 3 : lg - s_lo;
+        if (k == 3) lds_pass<3, true>(x, lg, nb, s_lo, twl);
+        else if (k == 2) lds_pass<2, true>(x, lg, nb, s_lo, twl);
+        else lds_pass<1, true>(x, lg, nb, s_lo, twl);
+        s_lo += k;
     }
 }
 
 // ------------------------------------------------- h-step kernel spectrum
 // Correlation y_m = sum_t W_t x_{m+t} with the h-fold one-step stencil has
 // DFT multiplier P(theta)^h, P(theta) = sum_t w_t e^{i t theta}.  Evaluated in
-// polar form in FP64: |P|^2 as rho^2 (1 + delta) with delta computed from
+// polar form in FP64: |P|^2 = rho^2 (1 + delta) with delta computed from
 // s = sin^2(theta/2) without cancellation, log1p for the magnitude and atan2
-// for the phase, so the h-th power costs O(1) and carries ~sqrt-free error.
+// for the phase, so the h-th power costs O(1) and its relative error does not
+// grow with h (repeated squaring would lose h ulps).
 //   binomial:  P = w_dn + w_up e^{i theta}                  (one-sided, offsets 0, 1)
 //   trinomial / BSM: P = w_m e^{-i theta} + w_c + w_p e^{i theta}  (centred)
-//   An exponential tilt beta (used only where a red segment spans a huge
-//   dynamic range) replaces the one-step weights w_t by w_t e^{beta t} and
-//   adds lscale to the log-magnitude.
-__device__ double2 kernel_power(const Desc &d, ll h, ll f, int lgN, double beta, double lscale)
+// An exponential tilt beta (used only where a red segment spans a huge
+// dynamic range) replaces w_t by w_t e^{beta t} and adds lscale to the
+// log-magnitude.  cos/sin of theta and sin(theta/2) come from the twiddle
+// table.
+struct Spec {
+    int bin;
+    double h, wa, wb, wc;  // binomial: (w_dn, w_up); centred: (w_m, w_c, w_p)
+    double rho, inv_rho2, lmag0, sp, df, cut;
+};
+
+__device__ __forceinline__ Spec make_spec(const Mp &p, ll h, double beta, double lscale)
 {
-    const ll N = ll(1) << lgN;
-    const ll ff = (f <= N / 2) ? f : f - N;
-    const double x = (double)ff / (double)N;  // theta / 2pi in (-1/2, 1/2]
-    const double sh = sinpi(x);
-    const double s = sh * sh;                  // sin^2(theta/2)
-    double sn, cs;
-    sincospi(2.0 * x, &sn, &cs);               // sin theta, cos theta
-    double rho, lg1p, arg;
-    if (d.model == BINOMIAL) {
-        const double wd = d.w0, wu = beta != 0.0 ? d.w1 * exp(beta) : d.w1;
-        rho = wd + wu;
-        lg1p = log1p(-4.0 * wd * wu * s / (rho * rho));
-        arg = atan2(wu * sn, wd + wu * cs);
+    Spec q;
+    q.bin = p.model == BINOMIAL;
+    q.h = (double)h;
+    if (q.bin) {
+        q.wa = p.w0;
+        q.wb = beta != 0.0 ? p.w1 * exp(beta) : p.w1;
+        q.wc = 0.0;
+        q.rho = q.wa + q.wb;
+        q.sp = 0.0;
+        q.df = 0.0;
     } else {
-        const double wm = beta != 0.0 ? d.w0 * exp(-beta) : d.w0, wc = d.w1;
-        const double wp = beta != 0.0 ? d.w2 * exp(beta) : d.w2;
-        rho = wm + wc + wp;
-        const double sp = wp + wm, df = wp - wm;
-        const double delta = (-4.0 * s * (rho * sp - df * df) + 16.0 * wp * wm * s * s) / (rho * rho);
-        lg1p = log1p(delta);
-        arg = atan2(df * sn, rho - 2.0 * sp * s);
+        q.wa = beta != 0.0 ? p.w0 * exp(-beta) : p.w0;
+        q.wb = p.w1;
+        q.wc = beta != 0.0 ? p.w2 * exp(beta) : p.w2;
+        q.rho = q.wa + q.wb + q.wc;
+        q.sp = q.wc + q.wa;
+        q.df = q.wc - q.wa;
     }
-    const double lrel = 0.5 * (double)h * lg1p;  // log(|P|^h / rho^h)
+    q.inv_rho2 = 1.0 / (q.rho * q.rho);
+    q.lmag0 = q.h * log(q.rho) + lscale;
+    q.cut = -120.0 / q.h;  // h delta / 2 < -60: below e^-60 of the kernel mass
+    return q;
+}
+
+__device__ __forceinline__ double2 kernel_power(const Spec &q, ll f, int lgN, const double2 *__restrict__ tw)
+{
+    const double2 e = tw[f << (LG_TW - lgN)];  // e^{-i theta}, theta = 2 pi f / N
+    const double cs = e.x, sn = -e.y;
+    double sh;
+    if (lgN < LG_TW) sh = tw[f << (LG_TW - 1 - lgN)].y;  // -sin(theta/2)
+    else sh = sinpi((double)f / (double)(ll(1) << lgN));
+    const double s = sh * sh;  // sin^2(theta/2)
+    double delta, arg;
+    if (q.bin) {
+        delta = -4.0 * q.wa * q.wb * s * q.inv_rho2;
+        if (delta < q.cut) return make_double2(0.0, 0.0);
+        arg = atan2(q.wb * sn, q.wa + q.wb * cs);
+    } else {
+        delta = (-4.0 * s * (q.rho * q.sp - q.df * q.df) + 16.0 * q.wc * q.wa * s * s) * q.inv_rho2;
+        if (delta < q.cut) return make_double2(0.0, 0.0);
+        arg = atan2(q.df * sn, q.rho - 2.0 * q.sp * s);
+    }
+    const double lrel = 0.5 * q.h * log1p(delta);
     if (!(lrel > -60.0)) return make_double2(0.0, 0.0);
-    const double mag = exp((double)h * log(rho) + lrel + lscale);
+    const double mag = exp(q.lmag0 + lrel);
     double ps, pc;
-    sincos((double)h * arg, &ps, &pc);
+    sincos(q.h * arg, &ps, &pc);
     return make_double2(mag * pc, mag * ps);
 }
 
@@ -190,13 +305,14 @@ __device__ __forceinline__ double tilt_out(double y, double beta, ll m)
 // spectrum is tilted to match and the output is untilted, y_m = y~_m e^{beta m}
 // (the e^{-beta tc} factor rides in the spectrum), so that a segment whose
 // values grow like e^{beta t} is transformed at uniform relative precision.
-__device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll n_in, ll h,
-                              ll out_off, ll n_out, double *__restrict__ dst, double2 *scr,
-                              double2 *lds, const double2 *__restrict__ tw, double beta = 0.0,
-                              double tc = 0.0)
+__device__ __forceinline__ void fft_correlate(Mp p, const double *__restrict__ src, ll n_in_, ll h_,
+                                           ll out_off_, ll n_out_, double *__restrict__ dst, double2 *scr,
+                                           double2 *lds, const double2 *__restrict__ tw, const double2 *twl,
+                                           double beta, double tc)
 {
+    const ll n_in = uni(n_in_), h = uni(h_), out_off = uni(out_off_), n_out = uni(n_out_);
     if (n_out <= 0) return;
-    const double lscale = -beta * tc;
+    const Spec q = make_spec(p, h, beta, -beta * tc);
     int lgN = ceil_log2(n_in);
     if (lgN < 1) lgN = 1;
     const ll N = ll(1) << lgN;
@@ -205,11 +321,16 @@ __device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll 
     if (lgN <= LG_NLDS) {
         for (int t = tid; t < N; t += WG) lds[t] = make_double2(t < n_in ? tilt_in(src[t], beta, t, tc) : 0.0, 0.0);
         __syncthreads();
-        lds_dif(lds, lgN, 1, tw);
-        for (int t = tid; t < N; t += WG)
-            lds[t] = cmul(lds[t], kernel_power(d, h, bitrev(t, lgN), lgN, beta, lscale));
+        lds_dif(lds, lgN, 1, twl);
+        // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
+        for (ll f = tid; f <= N / 2; f += WG) {
+            const double2 m = kernel_power(q, f, lgN, tw);
+            const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
+            lds[t1] = cmul(lds[t1], m);
+            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
+        }
         __syncthreads();
-        lds_dit_inv(lds, lgN, 1, tw);
+        lds_dit_inv(lds, lgN, 1, twl);
         for (ll t = tid; t < n_out; t += WG) dst[t] = tilt_out(lds[out_off + t].x * invN, beta, out_off + t);
         __syncthreads();
         return;
@@ -229,7 +350,7 @@ __device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll 
             lds[c * N1 + n1] = make_double2(idx < n_in ? tilt_in(src[idx], beta, idx, tc) : 0.0, 0.0);
         }
         __syncthreads();
-        lds_dif(lds, lg1, C, tw);
+        lds_dif(lds, lg1, C, twl);
         for (int t = tid; t < NLDS; t += WG) {
             const int c = t % C, p1 = t / C;
             const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
@@ -245,13 +366,13 @@ __device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll 
         double2 *row = scr + (ll)p1 * N2;
         for (int t = tid; t < N2; t += WG) lds[t] = row[t];
         __syncthreads();
-        lds_dif(lds, lg2, 1, tw);
+        lds_dif(lds, lg2, 1, twl);
         for (int t = tid; t < N2; t += WG) {
             const ll k2 = bitrev(t, lg2);
-            lds[t] = cmul(lds[t], kernel_power(d, h, k1 + (ll)N1 * k2, lgN, beta, lscale));
+            lds[t] = cmul(lds[t], kernel_power(q, k1 + (ll)N1 * k2, lgN, tw));
         }
         __syncthreads();
-        lds_dit_inv(lds, lg2, 1, tw);
+        lds_dit_inv(lds, lg2, 1, twl);
         for (int t = tid; t < N2; t += WG) row[t] = lds[t];
         __syncthreads();
     }
@@ -264,7 +385,7 @@ __device__ void fft_correlate(const Desc &d, const double *__restrict__ src, ll 
             lds[c * N1 + p1] = cmulc(scr[(ll)p1 * N2 + n2], w);
         }
         __syncthreads();
-        lds_dit_inv(lds, lg1, C, tw);
+        lds_dit_inv(lds, lg1, C, twl);
         for (int t = tid; t < NLDS; t += WG) {
             const int c = t % C, n1 = t / C;
             const ll idx = (ll)n1 * N2 + n20 + c;
@@ -286,40 +407,221 @@ __device__ __forceinline__ void count_conv(Stats *st, ll n_in, ll n_out)
     }
 }
 
+// ------------------------------------------------ direct correlation
+// For short steps the h-step correlation is evaluated as h applications of
+// the one-step linear stencil -- the backward recurrence itself without the
+// max, valid because every cell involved is a continuation cell.  One wave
+// holds the segment in registers (C cells per lane) and exchanges the edge
+// cells with wave shuffles.  Lattices: dst[t] = y_t (one-sided form); BSM:
+// dst[t] = z_{out_off + t} (centred form, out_off = h).
+template <int C>
+__device__ __forceinline__ void direct_wave(Mp p, const double *__restrict__ src, ll n_in_, ll h_, ll out_off_,
+                                         ll n_out_, double *__restrict__ dst)
+{
+    const ll n_in = uni(n_in_), h = uni(h_), out_off = uni(out_off_), n_out = uni(n_out_);
+    const int l = threadIdx.x & 63;
+    double v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const ll idx = (ll)l * C + c;
+        v[c] = idx < n_in ? src[idx] : 0.0;
+    }
+    const double w0 = p.w0, w1 = p.w1, w2 = p.w2;
+    if (p.model == BINOMIAL) {
+        for (ll k = 0; k < h; ++k) {
+            const double nb = dpp_dn1(v[0], 0.0);
+#pragma unroll
+            for (int c = 0; c < C - 1; ++c) v[c] = w0 * v[c] + w1 * v[c + 1];
+            v[C - 1] = w0 * v[C - 1] + w1 * nb;
+        }
+    } else if (p.model == TRINOMIAL) {
+        for (ll k = 0; k < h; ++k) {
+            const double n0 = dpp_dn1(v[0], 0.0), n1 = dpp_dn1(v[1], 0.0);
+#pragma unroll
+            for (int c = 0; c < C - 2; ++c) v[c] = w0 * v[c] + w1 * v[c + 1] + w2 * v[c + 2];
+            v[C - 2] = w0 * v[C - 2] + w1 * v[C - 1] + w2 * n0;
+            v[C - 1] = w0 * v[C - 1] + w1 * n0 + w2 * n1;
+        }
+    } else {
+        for (ll k = 0; k < h; ++k) {
+            const double pv = dpp_up1(v[C - 1], 0.0), nv = dpp_dn1(v[0], 0.0);
+            double prev = pv;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double cur = v[c];
+                const double nxt = (c + 1 < C) ? v[c + 1] : nv;
+                v[c] = w0 * prev + w1 * cur + w2 * nxt;
+                prev = cur;
+            }
+        }
+    }
+    const ll off = (p.model == BSM) ? out_off : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const ll idx = (ll)l * C + c - off;
+        if (idx >= 0 && idx < n_out) dst[idx] = v[c];
+    }
+}
+
+#define DIRECT_MAX_H 160   // longest step count evaluated by direct stepping
+#define DIRECT_MAX_N 1024  // longest segment (64 lanes x 16 cells)
+
+__device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
+
+// Dispatch: direct stepping for short kernels, FFT correlation otherwise.
+__device__ __forceinline__ void correlate(Stats *st, const Mp &p, const double *__restrict__ src, ll n_in, ll h,
+                                          ll out_off, ll n_out, double *__restrict__ dst, double2 *scr,
+                                          double2 *lds, const double2 *__restrict__ tw, const double2 *twl,
+                                          double beta = 0.0, double tc = 0.0)
+{
+    if (n_out <= 0) return;
+    const ll t0 = clk();
+    if (beta == 0.0 && h <= DIRECT_MAX_H && n_in <= DIRECT_MAX_N) {
+        if (threadIdx.x < 64) {
+            if (n_in <= 128) direct_wave<2>(p, src, n_in, h, out_off, n_out, dst);
+            else if (n_in <= 256) direct_wave<4>(p, src, n_in, h, out_off, n_out, dst);
+            else if (n_in <= 512) direct_wave<8>(p, src, n_in, h, out_off, n_out, dst);
+            else direct_wave<16>(p, src, n_in, h, out_off, n_out, dst);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && st) {
+            st->n_direct += 1;
+            st->cyc_direct += clk() - t0;
+        }
+        return;
+    }
+    fft_correlate(p, src, n_in, h, out_off, n_out, dst, scr, lds, tw, twl, beta, tc);
+    if (threadIdx.x == 0 && st) {
+        st->n_fft += 1;
+        st->cyc_fft += clk() - t0;
+    }
+}
+
 // ------------------------------------------------------------ band walkers
 // Executed by the 64 lanes of wave 0.  Lane l holds one cell of the current
-// row; the neighbour a row step needs comes from the next lane, and cells
-// beyond the band are exercise cells evaluated in closed form.  Each row's
-// last continuation cell is found with a ballot; the boundary is kept within
-// one cell per row of the previous one (Corollary 2.6 / Theorem 4.2), which
-// only overrides the ballot at ties within rounding.
+// row; the neighbour a row step needs comes from the next lane by a DPP wave
+// shift, and the cell beyond the band (an exercise cell) rides in as the
+// shift's fill value.  Exercise values are carried per lane by one
+// multiplication per row (S u^{col-i} gains a factor u per row down) and
+// re-seeded with exp() every RESEED rows.
+//
+// Boundary tracking uses the structure the paper proves: from one row to the
+// next the last continuation cell either stays or moves one cell towards the
+// root's side (Corollary 2.6, Theorem 4.2).  So each row only tests the ballot
+// bit of the previous boundary cell: set -> the boundary stays, clear -> it
+// drops by one.  This is the rule the oracle's last-red scan follows wherever
+// the red cells are contiguous; the two can differ only where rounding makes a
+// near-tie cell flip.  Per-row boundaries are collected (one row per lane, 64
+// rows per store) only when the caller asks for them.
+#define RESEED 64
+
+__device__ __forceinline__ unsigned long long row_mask(int last_lane)  // lanes 0..last_lane
+{
+    if (last_lane < 0) return 0ull;
+    if (last_lane >= 63) return ~0ull;
+    return (1ull << (last_lane + 1)) - 1ull;
+}
+
+__device__ __forceinline__ double vmax_f64(double a, double b)
+{
+    double r;
+    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;  // IEEE maxNum: a NaN operand yields the other one
+}
+
+// Lane `lane` of the result takes the (uniform) value `val`; other lanes keep `dst`.
+__device__ __forceinline__ unsigned writelane(unsigned dst, unsigned val, int lane)
+{
+    return ((int)(threadIdx.x & 63) == lane) ? val : dst;
+}
+__device__ __forceinline__ int clz64_lane(unsigned lo, unsigned hi)  // per-lane clz of (hi:lo), 64 if zero
+{
+    return hi ? (int)__clz(hi) : (lo ? 32 + (int)__clz(lo) : 64);
+}
+
+// Resolve the boundaries of a block of nb rows (lane r holds the ballot mask
+// of block row r in (mhi:mlo); `first` = column/offset of lane 0's cell in
+// that row).  Fast path: every mask is a contiguous run of lanes 0..last and
+// every row moves the boundary by 0 or -1 from the previous one -- the
+// structure of Corollary 2.6 / Theorem 4.2 -- so the boundary of row r is the
+// run's last cell, found for all rows at once.  Otherwise the previous-cell
+// rule is applied row by row (only at rounding-level ties or all-red rows).
+// Returns the boundary after the block; lane r of *bq receives row r's.
+template <bool TRI_ALLRED>
+__device__ __forceinline__ int resolve_block(unsigned mlo, unsigned mhi, int nb, int bc_in, int first,
+                                             int first_step, int lo_clamp_lane, int *bq, int tri_i_top)
+{
+    const int l = threadIdx.x & 63;
+    const int fr = first + first_step * l;  // cell of lane 0 in row l
+    const int z = clz64_lane(mlo, mhi);
+    const int last = fr + 63 - z;           // z = 64 -> fr - 1 (empty)
+    const unsigned long long want = (z == 64) ? 0ull : (~0ull >> z);
+    const unsigned long long got = ((unsigned long long)mhi << 32) | mlo;
+    const int prev = __shfl_up(last, 1, 64);
+    const int pv = (l == 0) ? bc_in : prev;
+    const bool ok = (l >= nb) || ((got == want) && (last == pv || last == pv - 1) && (last - fr >= lo_clamp_lane));
+    if (__ballot(!ok) == 0ull) {
+        *bq = last;
+        return __builtin_amdgcn_readlane(last, nb - 1);
+    }
+    // general rule, row by row
+    int bc = bc_in;
+    int q = 0;
+    for (int r = 0; r < nb; ++r) {
+        const unsigned long long m = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)mhi, r) << 32) |
+                                     (unsigned)__builtin_amdgcn_readlane((int)mlo, r);
+        const int f0 = first + first_step * r;
+        if (TRI_ALLRED && bc >= tri_i_top - 2 * r) {  // previous row entirely red (trinomial)
+            const int rowlast = tri_i_top - 2 * r - 2 - f0;  // lane of column 2i
+            const unsigned long long mm = m & (rowlast >= 63 ? ~0ull : (rowlast < 0 ? 0ull : ((1ull << (rowlast + 1)) - 1ull)));
+            bc = mm ? f0 + 63 - (int)__clzll(mm) : f0 - 1;
+        } else {
+            const int lb = bc - f0;
+            if (lb >= 0 && lb < 64) bc -= ((m >> lb) & 1ull) ? 0 : 1;
+        }
+        q = (l == r) ? bc : q;
+    }
+    *bq = q;
+    return bc;
+}
 
 // Binomial: rows i0-1 .. i0-h from row i0, whose red cells are [c0, b]
 // (b - c0 + 1 <= BAND); columns >= c0 only.  Writes the red cells of row i0-h
 // to dst, the boundary of each row to bnd (may be NULL); returns the last red
 // column of row i0-h.  *v0 receives the final value of column c0.
-__device__ ll band_bin(const Desc &d, ll i0, ll c0, ll h, ll b, const double *src, double *dst,
-                       ll *bnd, double *v0)
+__device__ __forceinline__ ll band_bin(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
+                                       ll *bnd, double *v0)
 {
+    // indices fit in 32 bits (T <= 2^21): scalar 32-bit bookkeeping
+    const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
     const int l = threadIdx.x & 63;
-    const ll j = c0 + l;
-    double g = (j <= b) ? src[j] : ((j <= i0) ? ex_bin(d, i0, j) : 0.0);
-    ll bc = b;
-    for (ll k = 1; k <= h; ++k) {
-        const ll i = i0 - k;
-        double gn = __shfl_down(g, 1, 64);
-        if (l == 63) gn = ex_bin(d, i + 1, c0 + BAND);  // exercise cell beyond the band
-        const double c = d.w0 * g + d.w1 * gn;
-        const double e = ex_bin(d, i, j);
-        const bool red = (j <= i) && red_of(c, e);
-        g = red ? c : e;
-        const unsigned long long m = __ballot(red);
-        const ll last = m ? c0 + 63 - __clzll(m) : c0 - 1;
-        ll bn = last < bc - 1 ? bc - 1 : (last > bc ? bc : last);
-        if (bn > i) bn = i;
-        if (bn < c0 - 1) bn = c0 - 1;
-        bc = bn;
-        if (bnd && l == 0) bnd[i] = bc;
+    const int j = c0 + l;
+    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1;
+    const double u = exp(a);
+    double g = (j <= b) ? src[j] : ((j <= i0) ? S * exp((double)(2 * j - i0) * a) - K : 0.0);
+    int bc = b;
+    for (int k0 = 0; k0 < h; k0 += 64) {
+        const int nb = (h - k0) < 64 ? (h - k0) : 64;
+        const int itop = i0 - k0;                             // row above the block
+        double x = S * exp((double)(2 * j - itop) * a);           // S u^{2j-i}, row itop
+        double xn = S * exp((double)(2 * (c0 + BAND) - itop) * a);  // column c0+64
+        unsigned mlo = 0, mhi = 0;
+#pragma unroll 4
+        for (int r = 0; r < nb; ++r) {
+            const double gn = dpp_dn1(g, xn - K);  // exercise cell beyond the band
+            x *= u;
+            xn *= u;
+            const double c = fma(w1, gn, w0 * g);
+            const double e = x - K;
+            g = vmax_f64(c, e);
+            // lanes beyond the row's last column (j > i) are outside the tree
+            const unsigned long long m = __ballot(c >= e) & row_mask(itop - 1 - r - c0);
+            mlo = writelane(mlo, (unsigned)m, r);
+            mhi = writelane(mhi, (unsigned)(m >> 32), r);
+        }
+        int q;
+        bc = resolve_block<false>(mlo, mhi, nb, bc, c0, 0, -1, &q, 0);
+        if (bnd && l < nb) bnd[itop - 1 - l] = q;
     }
     if (j <= bc) dst[j] = g;
     if (v0 && l == 0) *v0 = g;
@@ -327,40 +629,42 @@ __device__ ll band_bin(const Desc &d, ll i0, ll c0, ll h, ll b, const double *sr
 }
 
 // Trinomial: as band_bin; row i has columns 0..2i and each cell reads j, j+1,
-// j+2.  Below an all-red row the boundary drops by two (the row shrinks), so
-// the one-cell clamp only applies when the previous row had an exercise cell.
-__device__ ll band_tri(const Desc &d, ll i0, ll c0, ll h, ll b, const double *src, double *dst,
-                       ll *bnd, double *v0)
+// j+2.  Below an entirely red row the row shrinks by two cells, and the
+// boundary is the row's last red cell.
+__device__ __forceinline__ ll band_tri(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
+                                       ll *bnd, double *v0)
 {
+    const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
     const int l = threadIdx.x & 63;
-    const ll j = c0 + l;
-    double g = (j <= b) ? src[j] : ((j <= 2 * i0) ? ex_tri(d, i0, j) : 0.0);
-    ll bc = b;
-    for (ll k = 1; k <= h; ++k) {
-        const ll i = i0 - k;
-        double g1 = __shfl_down(g, 1, 64);
-        double g2 = __shfl_down(g, 2, 64);
-        if (l == 63) {
-            g1 = ex_tri(d, i + 1, c0 + BAND);
-            g2 = ex_tri(d, i + 1, c0 + BAND + 1);
-        } else if (l == 62) {
-            g2 = ex_tri(d, i + 1, c0 + BAND);
+    const int j = c0 + l;
+    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1, w2 = p.w2;
+    const double u = exp(a);
+    double g = (j <= b) ? src[j] : ((j <= 2 * i0) ? S * exp((double)(j - i0) * a) - K : 0.0);
+    int bc = b;
+    for (int k0 = 0; k0 < h; k0 += 64) {
+        const int nb = (h - k0) < 64 ? (h - k0) : 64;
+        const int itop = i0 - k0;
+        double x = S * exp((double)(j - itop) * a);           // S u^{j-i}, row itop
+        double x1 = S * exp((double)(c0 + BAND - itop) * a);  // column c0+64
+        double x2 = x1 * u;                                   // column c0+65
+        unsigned mlo = 0, mhi = 0;
+#pragma unroll 4
+        for (int r = 0; r < nb; ++r) {
+            const double g1 = dpp_dn1(g, x1 - K);   // lane 63: column c0+64
+            const double g2 = dpp_dn1(g1, x2 - K);  // lane 62: c0+64, lane 63: c0+65
+            x *= u;
+            x1 *= u;
+            x2 *= u;
+            const double c = fma(w2, g2, fma(w1, g1, w0 * g));
+            const double e = x - K;
+            g = vmax_f64(c, e);
+            const unsigned long long m = __ballot(c >= e) & row_mask(2 * (itop - 1 - r) - c0);
+            mlo = writelane(mlo, (unsigned)m, r);
+            mhi = writelane(mhi, (unsigned)(m >> 32), r);
         }
-        const double c = d.w0 * g + d.w1 * g1 + d.w2 * g2;
-        const double e = ex_tri(d, i, j);
-        const bool red = (j <= 2 * i) && red_of(c, e);
-        g = red ? c : e;
-        const unsigned long long m = __ballot(red);
-        const ll last = m ? c0 + 63 - __clzll(m) : c0 - 1;
-        ll bn;
-        if (bc >= 2 * (i + 1))
-            bn = last;  // previous row entirely red
-        else
-            bn = last < bc - 1 ? bc - 1 : (last > bc ? bc : last);
-        if (bn > 2 * i) bn = 2 * i;
-        if (bn < c0 - 1) bn = c0 - 1;
-        bc = bn;
-        if (bnd && l == 0) bnd[i] = bc;
+        int q;
+        bc = resolve_block<true>(mlo, mhi, nb, bc, c0, 0, -1, &q, 2 * itop);
+        if (bnd && l < nb) bnd[itop - 1 - l] = q;
     }
     if (j <= bc) dst[j] = g;
     if (v0 && l == 0) *v0 = g;
@@ -373,41 +677,52 @@ __device__ ll band_tri(const Desc &d, ll i0, ll c0, ll h, ll b, const double *sr
 // dependency cone), its left part stays inside the exercise region (needs
 // R0 - f <= 62).  Writes the red cells of step n0+h, up to R0-h, to dst and
 // returns the last exercise offset of step n0+h.  *vr receives the value of
-// the rightmost cell (the apex when R0 - h = 0).
-__device__ ll band_bsm(const Desc &d, ll n0, ll f, ll h, ll R0, const double *src, double *dst,
-                       ll *bnd, double *vr)
+// the rightmost cell (the apex when R0 - h = 0).  Here the boundary is the
+// last exercise (green) cell; it stays or moves one cell left per step
+// (Theorem 4.2).
+__device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const double *src, double *dst,
+                                       ll *bnd, double *vr)
 {
+    // offsets k lie in [-2T-1, T+1]: 32-bit scalar bookkeeping
+    const int n0 = (int)uni(n0_), f = (int)uni(f_), h = (int)uni(h_), R0 = (int)uni(R0_);
     const int l = threadIdx.x & 63;
-    const ll T = d.T;
-    ll base = R0 - 63;
-    ll k = base + l;
-    double v = (k <= f) ? ex_bsm(d, k) : src[k];
-    ll fc = f;
-    for (ll t = 1; t <= h; ++t) {
-        base -= 1;
-        k = base + l;
-        // new cell k needs old cells k-1, k, k+1 = old lanes l-2, l-1, l
-        double vm2 = __shfl_up(v, 2, 64);
-        double vm1 = __shfl_up(v, 1, 64);
-        if (l == 0) {
-            vm2 = ex_bsm(d, k - 1);
-            vm1 = ex_bsm(d, k);
-        } else if (l == 1) {
-            vm2 = ex_bsm(d, k - 1);
+    const int T = (int)p.T;
+    const double w0 = p.w0, w1 = p.w1, w2 = p.w2, s0 = p.s0, ds = p.a;
+    const double ud = exp(-ds);  // e^{-ds}: one cell to the left
+    int base = R0 - 63;
+    int k = base + l;
+    double v = (k <= f) ? 1.0 - exp(s0 + (double)k * ds) : src[k];
+    int fc = f;
+    for (int t0 = 0; t0 < h; t0 += 64) {
+        const int nb = (h - t0) < 64 ? (h - t0) : 64;
+        const int base0 = base;                      // band base before the block
+        double x = exp(s0 + (double)(base0 + l) * ds);  // e^{s_k} of the lane's cell before the block
+        unsigned mlo = 0, mhi = 0;
+#pragma unroll 4
+        for (int r = 0; r < nb; ++r) {
+            x *= ud;                   // the lane's new cell is one to the left
+            const double xm = x * ud;  // e^{s_{k-1}}
+            // new cell k needs old cells k-1, k, k+1 = old lanes l-2, l-1, l;
+            // lane 0 takes exercise values for the cells left of the band.
+            const double vm1 = dpp_up1(v, 1.0 - x);
+            const double vm2 = dpp_up1(vm1, 1.0 - xm);
+            const double cont = fma(w2, v, fma(w1, vm1, w0 * vm2));
+            const double g = 1.0 - x;
+            v = vmax_f64(cont, g);
+            const unsigned long long m = __ballot(g > cont);
+            mlo = writelane(mlo, (unsigned)m, r);
+            mhi = writelane(mhi, (unsigned)(m >> 32), r);
         }
-        const double cont = d.w0 * vm2 + d.w1 * vm1 + d.w2 * v;
-        const double g = ex_bsm(d, k);
-        const bool green = g > cont;
-        v = green ? g : cont;
-        const unsigned long long m = __ballot(green);
-        const ll last = m ? base + 63 - __clzll(m) : base - 1;
-        ll fn = last < fc - 1 ? fc - 1 : (last > fc ? fc : last);
-        fc = fn;
-        if (bnd && l == 0) {
-            const ll n = n0 + t;
-            bnd[n] = (fc < -(T - n)) ? BSM_NONE : (fc > T - n ? T - n : fc);
+        base -= nb;
+        int q;
+        // row r of the block has lane 0 at cell base0 - 1 - r
+        fc = resolve_block<false>(mlo, mhi, nb, fc, base0 - 1, -1, 0, &q, 0);
+        if (bnd && l < nb) {
+            const int n = n0 + t0 + 1 + l;
+            bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
         }
     }
+    k = base + l;
     if (k > fc && k <= R0 - h) dst[k] = v;
     if (vr && l == 63) *vr = v;
     return fc;
@@ -426,7 +741,7 @@ struct Frame {
 };
 
 struct Ctx {
-    const Desc *d;
+    Mp p;
     Stats *st;  // work counters in LDS (updated by lane 0 only)
     double *lo, *hi;  // this option's workspace (doubles) for range checks
     double *arena;
@@ -434,6 +749,7 @@ struct Ctx {
     double2 *scr;
     double2 *lds;
     const double2 *tw;
+    const double2 *twl;
     ll *bnd;
 };
 
@@ -446,10 +762,10 @@ __device__ __forceinline__ bool in_ws(const Ctx &cx, const double *p, ll first, 
 // Solve one trapezoid (model-dependent geometry, see the frame stages below)
 // and return the boundary of its last row.  All lanes call it; control flow is
 // uniform.  On a failed range check the error is stored in *err.
-__device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh, ll *ret_sh,
+__device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh, ll *ret_sh,
                               int *err_sh, ll *leaf_sh)
 {
-    const Desc &d = *cx.d;
+    const Mp d = cx.p;
     const int tid = threadIdx.x;
     const int span = (d.model == BINOMIAL) ? 1 : 2;  // columns consumed per row (lattices)
     if (tid == 0) {
@@ -461,7 +777,12 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
         const int s = *sp_sh;
         if (s < 0 || *err_sh) break;
         Frame fr = stk[s];
-        const ll rv = *ret_sh;
+        fr.r0 = uni(fr.r0);
+        fr.c0 = uni(fr.c0);
+        fr.h = uni(fr.h);
+        fr.b = uni(fr.b);
+        fr.aoff = uni(fr.aoff);
+        const ll rv = uni(*ret_sh);
         __syncthreads();
         bool pop = false;
         ll result = 0;
@@ -478,6 +799,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) {
                         e = DEV_RANGE;
                     } else {
+                        const ll tb = clk();
                         if (tid < 64) {
                             const ll r = (d.model == BINOMIAL)
                                              ? band_bin(d, i0, c0, h, b, fr.src, fr.dst, cx.bnd, nullptr)
@@ -485,6 +807,7 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                             if (tid == 0) {
                                 *leaf_sh = r;
                                 cx.st->band_rows += h;
+                                cx.st->cyc_band += clk() - tb;
                             }
                         }
                         __syncthreads();
@@ -498,8 +821,8 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     else if (!in_ws(cx, fr.src, c0, b)) e = DEV_RANGE;
                     else {
                         count_conv(cx.st, nred, nred - span * h1);
-                        fft_correlate(d, fr.src + c0, nred, h1, (span == 1) ? 0 : h1, nred - span * h1,
-                                      mid + c0, cx.scr, cx.lds, cx.tw);
+                        correlate(cx.st, d, fr.src + c0, nred, h1, (span == 1) ? 0 : h1, nred - span * h1,
+                                      mid + c0, cx.scr, cx.lds, cx.tw, cx.twl);
                         fr.mid = mid;
                         fr.stage = 1;
                         // (2) sub-trapezoid on the last span*h1 red cells of row i0
@@ -514,8 +837,8 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                 else {
                     count_conv(cx.st, n2, n2 - span * h2);
                     if (n2 - span * h2 > 0)
-                        fft_correlate(d, fr.mid + c0, n2, h2, (span == 1) ? 0 : h2, n2 - span * h2,
-                                      fr.dst + c0, cx.scr, cx.lds, cx.tw);
+                        correlate(cx.st, d, fr.mid + c0, n2, h2, (span == 1) ? 0 : h2, n2 - span * h2,
+                                      fr.dst + c0, cx.scr, cx.lds, cx.tw, cx.twl);
                     fr.ret1 = br;
                     fr.stage = 2;
                     // (4) sub-trapezoid on the last span*h2 red cells of row r
@@ -537,11 +860,13 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) {
                         e = DEV_RANGE;
                     } else {
+                        const ll tb = clk();
                         if (tid < 64) {
                             const ll r = band_bsm(d, n, f, h, f + 2 * h, fr.src, fr.dst, cx.bnd, nullptr);
                             if (tid == 0) {
                                 *leaf_sh = r;
                                 cx.st->band_rows += h;
+                                cx.st->cyc_band += clk() - tb;
                             }
                         }
                         __syncthreads();
@@ -557,8 +882,8 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                     else {
                         // conv 1: red cells [f+1, f+2h] -> [f+1+h1, f+2h-h1] of step n+h1
                         count_conv(cx.st, 2 * h, 2 * h - 2 * h1);
-                        fft_correlate(d, fr.src + f + 1, 2 * h, h1, h1, 2 * h - 2 * h1, mid + f + 1 + h1,
-                                      cx.scr, cx.lds, cx.tw);
+                        correlate(cx.st, d, fr.src + f + 1, 2 * h, h1, h1, 2 * h - 2 * h1, mid + f + 1 + h1,
+                                      cx.scr, cx.lds, cx.tw, cx.twl);
                         fr.mid = mid;
                         fr.stage = 1;
                         child = Frame{n, f, h1, 0, fr.aoff + 2 * h, 0, fr.src, mid, nullptr, 0, 0};
@@ -572,8 +897,8 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
                 else {
                     // conv 2: red cells [f'+1, f+h+h2] of step n+h1 -> [f'+1+h2, f+h] of step n+h
                     count_conv(cx.st, nin, nin - 2 * h2);
-                    fft_correlate(d, fr.mid + fp + 1, nin, h2, h2, nin - 2 * h2, fr.dst + fp + 1 + h2,
-                                  cx.scr, cx.lds, cx.tw);
+                    correlate(cx.st, d, fr.mid + fp + 1, nin, h2, h2, nin - 2 * h2, fr.dst + fp + 1 + h2,
+                                  cx.scr, cx.lds, cx.tw, cx.twl);
                     fr.ret1 = fp;
                     fr.stage = 2;
                     child = Frame{n + h1, fp, h2, 0, fr.aoff + 2 * h, 0, fr.mid, fr.dst, nullptr, 0, 0};
@@ -606,15 +931,16 @@ __device__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh,
 }
 
 // --------------------------------------------------------------- drivers
-__device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
+__device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
                                 ll *ret_sh, int *err_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
-    const Desc &d = *cx.d;
+    const Mp d = cx.p;
     const ll T = d.T;
     const int tid = threadIdx.x;
     const bool bin = d.model == BINOMIAL;
     const ll wT = bin ? T : 2 * T;  // last column of row T
     // Expiry row T (red = out of the money: G^red = 0 >= G^green) and row T-1.
+    const ll tr0 = clk();
     ll lastT = -1, lastT1 = -1;
     for (ll j = tid; j <= wT; j += WG) {
         const double eT = bin ? ex_bin(d, T, j) : ex_tri(d, T, j);
@@ -644,6 +970,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
         cx.bnd[T] = lastT;
         cx.bnd[T - 1] = lastT1;
     }
+    if (tid == 0) cx.st->cyc_rows += clk() - tr0;
     ll i0 = T - 1, b = lastT1;
     double *src = rowA, *dst = rowB;
     if (T > 1 && (d.no_green || b == wT - (bin ? 1 : 2))) {
@@ -665,7 +992,7 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
             for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = bin ? i : 2 * i;
         const ll hh = T - 1;
         count_conv(cx.st, b + 1, 1);
-        fft_correlate(d, src, b + 1, hh, bin ? 0 : hh, 1, val_sh, cx.scr, cx.lds, cx.tw, beta, tc);
+        correlate(cx.st, d, src, b + 1, hh, bin ? 0 : hh, 1, val_sh, cx.scr, cx.lds, cx.tw, cx.twl, beta, tc);
         __syncthreads();
         return *val_sh;
     }
@@ -678,12 +1005,16 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
         }
         const ll nred = b + 1;
         if (nred <= BAND) {  // the band walks the leftover triangle to the root
-            if (tid == 0) cx.st->band_rows += i0;
+            const ll tb = clk();
             if (tid < 64) {
                 if (bin) band_bin(d, i0, 0, i0, b, src, dst, cx.bnd, val_sh);
                 else band_tri(d, i0, 0, i0, b, src, dst, cx.bnd, val_sh);
             }
             __syncthreads();
+            if (tid == 0) {
+                cx.st->band_rows += i0;
+                cx.st->cyc_band += clk() - tb;
+            }
             return *val_sh;
         }
         ll h = bin ? nred : nred / 2;
@@ -702,13 +1033,14 @@ __device__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame
     return p;
 }
 
-__device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
+__device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
                             ll *ret_sh, int *err_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
-    const Desc &d = *cx.d;
+    const Mp d = cx.p;
     const ll T = d.T;
     const int tid = threadIdx.x;
     const ll NONE = LLONG_MIN;
+    const ll tr0 = clk();
     // rows are indexed by k in [-2T-1, T+1] -> pointer offset 2T+1
     double *A = rowA + 2 * T + 1, *B = rowB + 2 * T + 1;
     ll f0 = NONE, f1 = NONE;
@@ -731,6 +1063,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
         cx.bnd[0] = f0;
         cx.bnd[1] = (T >= 1) ? f1 : NONE;
     }
+    if (tid == 0) cx.st->cyc_rows += clk() - tr0;
     ll n = 1, R = T - 1, L = -(T - 1);
     ll f = (f1 == NONE) ? L - 1 : f1;
     double *src = A, *dst = B;
@@ -745,7 +1078,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
                 for (ll m = n + 1 + tid; m <= T; m += WG) cx.bnd[m] = NONE;
             const ll hh = T - n;
             count_conv(cx.st, R - L + 1, 1);
-            fft_correlate(d, src + L, R - L + 1, hh, hh, 1, val_sh, cx.scr, cx.lds, cx.tw);
+            correlate(cx.st, d, src + L, R - L + 1, hh, hh, 1, val_sh, cx.scr, cx.lds, cx.tw, cx.twl);
             __syncthreads();
             return d.K * (*val_sh);
         }
@@ -757,9 +1090,13 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
         }
         const ll w = R - f;
         if (w <= BAND - 2) {  // the band walks the leftover cone to the apex
-            if (tid == 0) cx.st->band_rows += T - n;
+            const ll tb = clk();
             if (tid < 64) band_bsm(d, n, f, T - n, R, src, dst, cx.bnd, val_sh);
             __syncthreads();
+            if (tid == 0) {
+                cx.st->band_rows += T - n;
+                cx.st->cyc_band += clk() - tb;
+            }
             return d.K * (*val_sh);
         }
         ll h = w / 2;
@@ -770,7 +1107,7 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
         if (*err_sh) return NAN;
         // the rest of step n+h: red cells [f+1+h, R-h] from [f+1, R] of step n
         count_conv(cx.st, w, w - 2 * h);
-        fft_correlate(d, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h, cx.scr, cx.lds, cx.tw);
+        correlate(cx.st, d, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h, cx.scr, cx.lds, cx.tw, cx.twl);
         n += h;
         R -= h;
         L += h;
@@ -781,11 +1118,12 @@ __device__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *st
     }
 }
 
-__global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ descs, char *ws,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) solve_kernel(const Desc *__restrict__ descs, char *ws,
                                                    const double2 *__restrict__ tw, double *price,
                                                    ll *bnd, ll bnd_stride, int32_t *err, Stats *stats)
 {
     __shared__ double2 lds[NLDS];
+    __shared__ double2 twl[NLDS / 2];
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
     __shared__ ll ret_sh, leaf_sh, red_sh[WG / 64];
@@ -796,7 +1134,7 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     if (d.model < 0) {  // rejected on the host: no work, price NaN
         if (threadIdx.x == 0) {
             price[d.out_index] = NAN;
-            stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0};
+            stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         }
         return;
     }
@@ -806,7 +1144,7 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     double *arena = rowB + d.row_len;
     double2 *scr = (double2 *)(arena + d.arena_len);
     Ctx cx;
-    cx.d = &d;
+    cx.p = make_mp(d);
     cx.lo = rowA;
     cx.hi = (double *)(scr + d.nfft);
     cx.arena = arena;
@@ -814,14 +1152,17 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     cx.scr = scr;
     cx.lds = lds;
     cx.tw = tw;
+    cx.twl = twl;
+    for (int t = threadIdx.x; t < NLDS / 2; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS)];
     cx.bnd = bnd ? bnd + d.out_index * bnd_stride : nullptr;
     cx.st = &st_sh;
     if (threadIdx.x == 0) {
         err_sh = 0;
         ret_sh = 0;
-        st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0};
+        st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     }
     __syncthreads();
+    const ll ttot = clk();
     double p;
     if (d.model == BSM)
         p = drive_bsm(cx, rowA, rowB, stk, &sp_sh, &ret_sh, &err_sh, &leaf_sh, red_sh, &val_sh);
@@ -831,6 +1172,7 @@ __global__ void __launch_bounds__(WG) solve_kernel(const Desc *__restrict__ desc
     if (threadIdx.x == 0) {
         price[d.out_index] = err_sh ? NAN : p;
         if (err) err[d.out_index] = err_sh;
+        st_sh.cyc_total = clk() - ttot;
         stats[d.out_index] = st_sh;
     }
 }

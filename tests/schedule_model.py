@@ -170,16 +170,14 @@ class Model:
             else:
                 c = d["w"][0] * g + d["w"][1] * gn1
             e = ex(d, i, j)
-            red = (j <= wmax(i)) & red_of(c, e)
-            g = np.where(red, c, e)
-            last = c0 + int(np.nonzero(red)[0].max()) if red.any() else c0 - 1
-            if tri and bc >= 2 * (i + 1):
-                bn = last
-            else:
-                bn = min(max(last, bc - 1), bc)
-            bn = min(bn, wmax(i))
-            bn = max(bn, c0 - 1)
-            bc = bn
+            red = c >= e
+            g = np.maximum(c, e)
+            if tri and bc >= 2 * (i + 1):  # previous row entirely red
+                rr = red & (j <= wmax(i))
+                bc = max(c0 + int(np.nonzero(rr)[0].max()) if rr.any() else c0 - 1, c0 - 1)
+            elif bc >= c0:  # the previous boundary cell stays red, or the boundary drops by one
+                if bc > wmax(i) or not red[bc - c0]:
+                    bc -= 1
             self.bnd[i] = bc
             self.band_rows += 1
         if bc >= c0:
@@ -203,9 +201,10 @@ class Model:
             cont = wm * vm2 + wc * vm1 + wp * v
             g = ex_bsm(d, k)
             green = g > cont
-            v = np.where(green, g, cont)
-            last = base + int(np.nonzero(green)[0].max()) if green.any() else base - 1
-            fc = min(max(last, fc - 1), fc)
+            v = np.maximum(cont, g)
+            lf = fc - base
+            if 0 <= lf < BAND and not green[lf]:
+                fc -= 1
             n = n0 + t
             self.bnd[n] = NONE if fc < -(T - n) else min(fc, T - n)
             self.band_rows += 1
