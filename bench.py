@@ -178,8 +178,12 @@ def main():
     }
     line["work"]["max_depth"] = int(st[:, F["max_depth"]].max())
     tot = float(st[:, F["cyc_total"]].sum()) or 1.0
-    line["phases"] = {k: float(st[:, F["cyc_" + k]].sum()) / tot for k in ("band", "direct", "fft", "rows")}
+    line["phases"] = {k: float(st[:, F["cyc_" + k]].sum()) / tot for k in ("band", "tiles", "wait", "rows")}
     line["phases"]["cycles_per_option"] = tot / max(n, 1)
+    pool = binding.pool_stats(L, n)
+    busy = pool["helper_busy"] + pool["helper_idle"]
+    line["pool"] = dict(pool, helper_busy_frac=(pool["helper_busy"] / busy) if busy else None,
+                        tuning=ctx.tuning())
     if args.plain:
         log("plain O(T^2) GPU stencil on the same batch ...")
         wsp = torch.empty(binding.plain_workspace_bytes(opts), dtype=torch.uint8, device="cuda")

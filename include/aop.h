@@ -145,18 +145,44 @@ typedef struct {
     int64_t trapezoids;   /* top-level trapezoids */
     int64_t n_direct;     /* correlations evaluated by direct stepping */
     int64_t n_fft;        /* correlations evaluated by FFT */
-    int64_t cyc_band;     /* shader clock cycles spent in the band stencil */
-    int64_t cyc_direct;   /* ... in direct-stepping correlations */
-    int64_t cyc_fft;      /* ... in FFT correlations */
+    int64_t cyc_band;     /* driver's shader clock cycles in the band stencil */
+    int64_t cyc_tiles;    /* ... computing correlation tiles itself */
+    int64_t cyc_wait;     /* ... waiting for tiles other workgroups took */
     int64_t cyc_rows;     /* ... computing the rows next to expiry */
-    int64_t cyc_total;    /* ... in the whole solve */
-    int64_t reserved;
+    int64_t cyc_total;    /* ... in the whole solve of the option */
+    int64_t n_published;  /* correlations handed to the work pool */
 } aop_stats;
 
 /* Copy the work counters of the last aop_price_batch on this workspace to the
  * host (synchronous; call after the stream has passed the batch).  h_stats:
  * n entries; entries of rejected options are zero. */
 aop_status aop_batch_stats(const void *d_workspace, int64_t n, aop_stats *h_stats);
+
+/* Work-pool counters of the last aop_price_batch on this workspace
+ * (synchronous): h_out[0] workgroups, [1] tiles computed by helper
+ * workgroups, [2] helper busy cycles, [3] helper idle cycles, [4] options
+ * finished, [5] 1 if the launch aborted (a wait passed its deadline or a job was refused), [6..7] 0. */
+aop_status aop_pool_stats(const void *d_workspace, int64_t n, int64_t h_out[8]);
+
+/*
+ * Launch tuning of the FFT path (per context; changes no result, only speed).
+ * The batch kernel is persistent: `workgroups` workgroups each drive one option
+ * at a time (largest first) and, once no option is left, compute tiles of the
+ * correlations other drivers publish (Sec. 2.3: the two correlations of a
+ * trapezoid are independent of its sub-trapezoids).
+ */
+typedef struct {
+    int32_t workgroups;     /* persistent grid (0 = one per compute unit, at most 1024) */
+    int32_t pub_min_lg;     /* FFT correlations of size >= 2^pub_min_lg are published (1..30) */
+    int32_t pub_direct;     /* 1: publish direct-stepping correlations too; 0: run them inline */
+    int32_t direct_max_h;   /* correlations with h <= this (and n <= direct_max_n) step directly */
+    int32_t direct_max_n;   /* <= 1024 */
+    int32_t helper_idle_us; /* a helper workgroup leaves after this long without work (>= 1) */
+    int64_t timeout_ms;     /* a wait longer than this aborts the launch: its options price NaN (> 0) */
+} aop_tuning;
+aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out);
+/* Returns AOP_EINVAL (and keeps the old tuning) for out-of-range fields. */
+aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *tuning);
 
 /* Synchronous convenience: price one option, allocating and freeing its own
  * workspace.  h_boundary: NULL or a host array of T+1 int64. */

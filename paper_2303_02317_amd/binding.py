@@ -25,11 +25,18 @@ BSM_NONE = np.iinfo(np.int64).min
 #: Every symbol include/aop.h declares.
 EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
-           "aop_status_str", "aop_version"]
+           "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
-                "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_direct", "cyc_fft", "cyc_rows", "cyc_total",
-                "reserved"]
+                "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
+                "n_published"]
+POOL_FIELDS = ["workgroups", "helper_tiles", "helper_busy", "helper_idle", "options_done", "aborted"]
+
+
+class AopTuning(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int32), ("pub_min_lg", ctypes.c_int32), ("pub_direct", ctypes.c_int32),
+                ("direct_max_h", ctypes.c_int32), ("direct_max_n", ctypes.c_int32),
+                ("helper_idle_us", ctypes.c_int32), ("timeout_ms", ctypes.c_int64)]
 
 
 class AopError(RuntimeError):
@@ -67,6 +74,9 @@ def load():
         "aop_sync": (I32, [P]),
         "aop_status_str": (ctypes.c_char_p, [I32]),
         "aop_version": (ctypes.c_char_p, []),
+        "aop_pool_stats": (I32, [P, I64, P]),
+        "aop_ctx_get_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
+        "aop_ctx_set_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -109,6 +119,21 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def tuning(self) -> dict:
+        t = AopTuning()
+        _check(load().aop_ctx_get_tuning(self._h, ctypes.byref(t)), "aop_ctx_get_tuning")
+        return {f: getattr(t, f) for f, _ in AopTuning._fields_}
+
+    def set_tuning(self, **kw):
+        """Change launch tuning fields (see aop_tuning); unknown fields raise."""
+        cur = self.tuning()
+        for k, v in kw.items():
+            if k not in cur:
+                raise KeyError(k)
+            cur[k] = int(v)
+        t = AopTuning(**cur)
+        _check(load().aop_ctx_set_tuning(self._h, ctypes.byref(t)), "aop_ctx_set_tuning")
 
     def close(self):
         if self._h:
@@ -210,6 +235,14 @@ def batch_stats(launch: "Launch", n: int) -> np.ndarray:
     _check(load().aop_batch_stats(ctypes.c_void_p(launch.workspace.data_ptr()), n,
                                   out.ctypes.data_as(ctypes.c_void_p)), "aop_batch_stats")
     return out[:n]
+
+
+def pool_stats(launch: "Launch", n: int) -> dict:
+    """Work-pool counters of a finished launch."""
+    out = np.zeros(8, dtype=np.int64)
+    _check(load().aop_pool_stats(ctypes.c_void_p(launch.workspace.data_ptr()), n,
+                                 out.ctypes.data_as(ctypes.c_void_p)), "aop_pool_stats")
+    return {f: int(out[i]) for i, f in enumerate(POOL_FIELDS)}
 
 
 def price_one(ctx: Context, opt, precision: int = AOP_FP64, boundary: bool = False):

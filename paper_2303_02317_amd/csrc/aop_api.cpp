@@ -26,6 +26,9 @@ struct aop_ctx {
     size_t stage_cap = 0;          // descriptors
     hipEvent_t stage_done = nullptr;
     bool stage_pending = false;
+    int n_cu = 0;                  // compute units of the device
+    double tick_hz = 1e8;          // device wall clock (s_memrealtime) frequency
+    aop_tuning tuning{};           // launch tuning of the solve kernel
 };
 
 namespace {
@@ -136,19 +139,35 @@ void geometry(Desc &d)
         nin_max = 2 * T + 1;
     }
     d.nfft = std::max<int64_t>(next_pow2(std::max<int64_t>(nin_max, 2)), 2);
+    // The correlations a driver has in flight at once use the scratch as a
+    // stack: one per recursion depth, each at most half the size of its
+    // parent's, plus (BSM) the top-level correlation beside the trapezoid.
+    d.scr_len = 4 * d.nfft;
 }
 
 size_t option_bytes(const Desc &d)
 {
-    return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.nfft);
+    return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.scr_len);
 }
 
-// Build descriptors for a batch; returns total workspace bytes.
+// Estimated solve cost of an option (work ~ T log^2 T; the trinomial and BSM
+// rows are twice as long), used to hand out the largest options first.
+double option_cost(const Desc &d)
+{
+    if (d.model < 0) return -1.0;
+    const double T = (double)d.T, lg = std::log2(T + 1.0);
+    return (d.model == aop::BINOMIAL ? 1.0 : 2.0) * T * (lg * lg + 1.0);
+}
+
+// Build descriptors for a batch; returns total workspace bytes.  Descriptors
+// are stored in decreasing order of estimated cost (the order in which the
+// persistent kernel's workgroups claim them); out_index keeps each option's
+// position in the caller's arrays.
 size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambda, Desc *out, int32_t *status)
 {
-    size_t off = (size_t)aop::stats_offset(n) + align_up(sizeof(aop::Stats) * (size_t)std::max<int64_t>(n, 1));
+    std::vector<Desc> tmp((size_t)std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; ++i) {
-        Desc &d = out[i];
+        Desc &d = tmp[(size_t)i];
         aop_status st = make_desc(opts[i], lambda, d);
         if (st == AOP_OK && prec != AOP_FP64) st = AOP_ENOTIMPL;
         d.out_index = i;
@@ -159,8 +178,20 @@ size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambd
             continue;
         }
         geometry(d);
-        d.ws_off = (int64_t)off;
-        off += option_bytes(d);
+    }
+    std::vector<int64_t> order((size_t)std::max<int64_t>(n, 0));
+    for (int64_t i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return option_cost(tmp[(size_t)a]) > option_cost(tmp[(size_t)b]);
+    });
+    size_t off = (size_t)aop::options_offset(n);
+    for (int64_t k = 0; k < n; ++k) {
+        Desc d = tmp[(size_t)order[(size_t)k]];
+        if (d.model >= 0) {
+            d.ws_off = (int64_t)off;
+            off += option_bytes(d);
+        }
+        out[k] = d;
     }
     return off;
 }
@@ -241,6 +272,20 @@ aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
         delete ctx;
         return AOP_ENOMEM;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
+        ncu = 1;
+    ctx->n_cu = ncu;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        ctx->tick_hz = 1e3 * (double)khz;
+    ctx->tuning.workgroups = std::min(ncu, aop::MAX_WG);
+    ctx->tuning.pub_min_lg = 12;
+    ctx->tuning.pub_direct = 0;
+    ctx->tuning.direct_max_h = 160;
+    ctx->tuning.direct_max_n = 1024;
+    ctx->tuning.helper_idle_us = 20000;
+    ctx->tuning.timeout_ms = 30000;
     if (hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess ||
         aop::launch_twiddles(ctx->d_tw, nullptr) != 0 || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(ctx->d_tw);
@@ -302,7 +347,16 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
         return AOP_EDEVICE;
     if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
     ctx->stage_pending = true;
-    if (aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr,
+    aop::Tune tune;
+    tune.workgroups = ctx->tuning.workgroups;
+    tune.pub_min_lg = ctx->tuning.pub_min_lg;
+    tune.pub_direct = ctx->tuning.pub_direct;
+    tune.direct_max_h = ctx->tuning.direct_max_h;
+    tune.direct_max_n = ctx->tuning.direct_max_n;
+    tune.reserved = 0;
+    tune.timeout_ticks = (int64_t)(1e-3 * (double)ctx->tuning.timeout_ms * ctx->tick_hz);
+    tune.idle_ticks = (int64_t)(1e-6 * (double)ctx->tuning.helper_idle_us * ctx->tick_hz);
+    if (aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr, tune,
                           stream) != 0)
         return AOP_EDEVICE;
     return AOP_OK;
@@ -386,6 +440,43 @@ aop_status aop_batch_stats(const void *d_ws, int64_t n, aop_stats *h_stats)
     return hipMemcpy(h_stats, src, sizeof(aop_stats) * (size_t)n, hipMemcpyDeviceToHost) == hipSuccess
                ? AOP_OK
                : AOP_EDEVICE;
+}
+
+aop_status aop_pool_stats(const void *d_ws, int64_t n, int64_t *h_out)
+{
+    if (!d_ws || !h_out || n < 0) return AOP_EINVAL;
+    aop::PoolHdr hdr;
+    if (hipMemcpy(&hdr, (const char *)d_ws + aop::pool_offset(n), sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+        return AOP_EDEVICE;
+    h_out[0] = hdr.n_wg;
+    h_out[1] = hdr.helper_tiles;
+    h_out[2] = hdr.helper_busy;
+    h_out[3] = hdr.helper_idle;
+    h_out[4] = (int64_t)(hdr.status & 0xffffffffull);
+    h_out[5] = (int64_t)(hdr.status >> 32);
+    h_out[6] = 0;
+    h_out[7] = 0;
+    return AOP_OK;
+}
+
+aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out)
+{
+    if (!ctx || !out) return AOP_EINVAL;
+    *out = ctx->tuning;
+    return AOP_OK;
+}
+
+aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *t)
+{
+    if (!ctx || !t) return AOP_EINVAL;
+    aop_tuning u = *t;
+    if (u.workgroups == 0) u.workgroups = std::min(ctx->n_cu, aop::MAX_WG);
+    if (u.workgroups < 1 || u.workgroups > aop::MAX_WG || u.pub_min_lg < 1 || u.pub_min_lg > 30 ||
+        u.direct_max_h < 0 || u.direct_max_n < 0 || u.direct_max_n > 1024 || u.helper_idle_us < 1 ||
+        u.timeout_ms <= 0 || u.timeout_ms > 3600000)
+        return AOP_EINVAL;
+    ctx->tuning = u;
+    return AOP_OK;
 }
 
 aop_status aop_sync(void *stream)

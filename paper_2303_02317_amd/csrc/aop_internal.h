@@ -12,7 +12,7 @@ constexpr int64_t BSM_NONE = INT64_MIN;
 
 // Error codes an option's kernel can record (in Desc::dev_err) when one of
 // its internal geometry checks fails; the option's price is then NaN.
-enum DevErr : int32_t { DEV_OK = 0, DEV_RANGE = 1, DEV_STACK = 2, DEV_ARENA = 3, DEV_FFT = 4 };
+enum DevErr : int32_t { DEV_OK = 0, DEV_RANGE = 1, DEV_STACK = 2, DEV_ARENA = 3, DEV_FFT = 4, DEV_TIMEOUT = 5, DEV_ABORT = 6 };
 
 // Per-option descriptor, built on the host from the paper's formulas and
 // copied to the device (128 bytes).
@@ -33,17 +33,53 @@ struct Desc {
     int64_t nfft;       // complex elements in the FFT scratch
     int64_t out_index;  // index of this option in the caller's arrays
     int64_t no_green;   // lattice call with Y = 0: no exercise cell below the expiry row (Lemma 2.3)
-    int64_t reserved;
+    int64_t scr_len;    // complex elements of FFT scratch (a stack shared by the outstanding correlations)
 };
 static_assert(sizeof(Desc) == 128, "descriptor is 128 bytes");
 
 // Per-option work counters (mirror of aop_stats), stored after the descriptors.
 struct Stats {
     int64_t convs, conv_in, conv_out, fft_points, band_rows, direct_cells, max_depth, trapezoids;
-    int64_t n_direct, n_fft, cyc_band, cyc_direct, cyc_fft, cyc_rows, cyc_total, reserved;
+    int64_t n_direct, n_fft, cyc_band, cyc_tiles, cyc_wait, cyc_rows, cyc_total, n_published;
 };
 static_assert(sizeof(Stats) == 128, "stats are 128 bytes");
 inline int64_t stats_offset(int64_t n) { return ((int64_t)sizeof(Desc) * (n > 0 ? n : 1) + 255) / 256 * 256; }
+
+// Work pool of the persistent solve kernel, after the stats region: a
+// 128-byte header, a summary bitmap (bit w: workgroup w has a job slot with
+// claimable tiles), one 64-bit word per workgroup whose bits flag those slots,
+// and JPW job slots per workgroup (128 B each).
+constexpr int JPW = 64;          // job slots per workgroup
+constexpr int MAX_WG = 1024;     // largest persistent grid
+struct PoolHdr {
+    uint32_t next_option, n_wg;
+    uint64_t status;  // options finished (low 32 bits) | launch aborted (bit 32)
+    int64_t helper_tiles, helper_busy, helper_idle;
+    int64_t reserved[11];
+};
+static_assert(sizeof(PoolHdr) == 128, "pool header is 128 bytes");
+constexpr int64_t JOB_BYTES = 128;
+constexpr int64_t POOL_SUMMARY = 128;                 // byte offset of the summary bitmap (MAX_WG bits)
+constexpr int64_t POOL_BITS = 256;                    // byte offset of the per-workgroup slot words
+constexpr int64_t POOL_JOBS = POOL_BITS + 8 * MAX_WG; // byte offset of the job slots
+constexpr int64_t POOL_BYTES = POOL_JOBS + JOB_BYTES * JPW * MAX_WG;
+inline int64_t pool_offset(int64_t n)
+{
+    return stats_offset(n) + ((int64_t)128 * (n > 0 ? n : 1) + 255) / 256 * 256;
+}
+inline int64_t options_offset(int64_t n) { return pool_offset(n) + POOL_BYTES; }
+
+// Launch-time tuning of the solve kernel (device clock units).
+struct Tune {
+    int32_t workgroups;    // persistent grid size
+    int32_t pub_min_lg;    // FFT correlations of size >= 2^pub_min_lg go to the pool
+    int32_t pub_direct;    // direct-stepping correlations go to the pool (1) or run inline (0)
+    int32_t direct_max_h;  // longest kernel evaluated by direct stepping
+    int32_t direct_max_n;  // longest segment evaluated by direct stepping (<= 1024)
+    int32_t reserved;
+    int64_t timeout_ticks; // wall-clock ticks a wait may take before the launch aborts
+    int64_t idle_ticks;    // wall-clock ticks a helper waits for work before it leaves
+};
 
 constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22
 constexpr int64_t TW_N = int64_t(1) << LG_TW;
@@ -51,7 +87,7 @@ constexpr int64_t TW_N = int64_t(1) << LG_TW;
 // Host-side launchers (defined in aop_solver.hip / aop_plain.hip).
 int launch_twiddles(void *d_tw, void *stream);
 int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price,
-                 int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, void *stream);
+                 int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, const Tune &tune, void *stream);
 int launch_plain_batch(const Desc *d_desc, const Desc *h_desc, int64_t n, char *d_ws, double *d_price,
                        void *stream);
 

@@ -1,19 +1,25 @@
 // aop_solver.hip -- gfx950 kernels of the FFT nonlinear-stencil pricer.
 //
-// One workgroup (256 lanes, 4 wave64) prices one option.  It
+// One persistent launch prices a batch of options.  Each workgroup (256
+// lanes, 4 wave64) claims an option and drives it:
 //   1. computes the expiry row and the first backward row directly (the
 //      corollary relating consecutive boundaries only holds below the top row),
 //   2. runs the trapezoid decomposition (Sec. 2.3 "Partitioning the triangle",
 //      Sec. 3 / appendix A.3, Sec. 4.3): each trapezoid is solved recursively
 //      ("Solving a trapezoid"); guaranteed-continuation (red) segments are
-//      advanced h rows at once by an FFT correlation with the h-step stencil
-//      kernel, whose spectrum is evaluated per bin in closed form (FP64);
+//      advanced h rows at once by a correlation with the h-step stencil kernel,
+//      by FFT with the kernel's spectrum evaluated per bin in closed form (FP64)
+//      or, for short kernels, by direct stepping of the linear stencil,
 //   3. solves the base cases with a one-wave band walker that applies the
 //      max(continuation, exercise) stencil directly, one lane per cell, and
 //      finds each row's boundary with a wave ballot.
-// The recursion runs on an explicit stack in LDS; control flow is uniform
-// across the workgroup.  Every range a step touches is checked against the
-// option's workspace first; a failed check records an error and prices NaN.
+// Correlations are published as tiled jobs in a work pool that every
+// workgroup without an option of its own (and each driver, for its own jobs)
+// takes tiles from, so that one option's transforms spread over the chip
+// while its driver walks the band.  The recursion runs on an explicit stack in
+// LDS; control flow is uniform across a workgroup.  Every range a step touches
+// is checked against the option's workspace first; a failed check records an
+// error and prices NaN.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <math.h>
@@ -296,115 +302,151 @@ __device__ __forceinline__ double tilt_out(double y, double beta, ll m)
     return beta == 0.0 ? y : y * exp(beta * (double)m);
 }
 
-// dst[t] = (x (*) W^(h))[out_off + t], t in [0, n_out), where x = src[0..n_in)
-// zero-padded to N = 2^ceil(log2 n_in) and (*) is the circular correlation of
-// the h-step kernel; for out_off + n_out <= n_in - span the window never wraps.
-// Whole workgroup.  N <= 2048: in LDS.  Larger N: four-step with N = N1 * 2048
-// through the global scratch `scr` (N complex).
-// With beta != 0 the input is tilted, x~_t = x_t e^{-beta (t - tc)}, the kernel
-// spectrum is tilted to match and the output is untilted, y_m = y~_m e^{beta m}
-// (the e^{-beta tc} factor rides in the spectrum), so that a segment whose
-// values grow like e^{beta t} is transformed at uniform relative precision.
-__device__ __forceinline__ void fft_correlate(Mp p, const double *__restrict__ src, ll n_in_, ll h_,
-                                           ll out_off_, ll n_out_, double *__restrict__ dst, double2 *scr,
-                                           double2 *lds, const double2 *__restrict__ tw, const double2 *twl,
-                                           double beta, double tc)
+// A correlation job computes dst[t] = (x (*) W^(h))[out_off + t], t < n_out,
+// where x = src[0..n_in) zero-padded to N = 2^lgN and (*) is the circular
+// correlation with the h-step stencil kernel; for out_off + n_out <= n_in -
+// span the window never wraps, so the result is the linear one.  Kinds:
+//   K_DIRECT  h applications of the one-step linear stencil in one wave;
+//   K_LDS     one transform in LDS (N <= 2048);
+//   K_4STEP   N = N1 x 2048 through the global scratch `scr` (N complex), in
+//             three phases of N1 tiles each:
+//     phase 0, tile t: length-N1 column transforms of columns [tC, tC + C)
+//                      (C = 2048 / N1) of the N1 x 2048 row-major view, times
+//                      w_N^{n2 k1}; rows are left in bit-reversed k1 order;
+//     phase 1, tile t: row t: forward length-2048 transform, product with the
+//                      kernel power at frequency k1 + N1 k2, inverse;
+//     phase 2, tile t: conjugate twiddle, inverse column transforms, output.
+// Tiles of one phase are independent; a phase starts once the previous one
+// has completed.  With beta != 0 the input is tilted, x~_t = x_t e^{-beta (t -
+// tc)}, the kernel spectrum is tilted to match and the output untilted, y_m =
+// y~_m e^{beta m} (the e^{-beta tc} factor rides in the spectrum), so that a
+// segment growing like e^{beta t} is transformed at uniform relative precision.
+enum { K_DIRECT = 0, K_LDS = 1, K_4STEP = 2 };
+
+struct JobArgs {
+    const double *src;
+    double *dst;
+    double2 *scr;
+    ll n_in, h, out_off, n_out;
+    double beta, tc;
+    int desc, lgN, kind, ntile, nph, pad;
+};
+static_assert(sizeof(JobArgs) == 96, "job arguments are 96 bytes");
+
+__device__ __forceinline__ JobArgs uni_args(JobArgs a)
 {
-    const ll n_in = uni(n_in_), h = uni(h_), out_off = uni(out_off_), n_out = uni(n_out_);
-    if (n_out <= 0) return;
-    const Spec q = make_spec(p, h, beta, -beta * tc);
-    int lgN = ceil_log2(n_in);
-    if (lgN < 1) lgN = 1;
-    const ll N = ll(1) << lgN;
-    const double invN = 1.0 / (double)N;
-    const int tid = threadIdx.x;
-    if (lgN <= LG_NLDS) {
-        for (int t = tid; t < N; t += WG) lds[t] = make_double2(t < n_in ? tilt_in(src[t], beta, t, tc) : 0.0, 0.0);
-        __syncthreads();
-        lds_dif(lds, lgN, 1, twl);
-        // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
-        for (ll f = tid; f <= N / 2; f += WG) {
-            const double2 m = kernel_power(q, f, lgN, tw);
-            const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
-            lds[t1] = cmul(lds[t1], m);
-            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
-        }
-        __syncthreads();
-        lds_dit_inv(lds, lgN, 1, twl);
-        for (ll t = tid; t < n_out; t += WG) dst[t] = tilt_out(lds[out_off + t].x * invN, beta, out_off + t);
-        __syncthreads();
-        return;
-    }
-    const int lg2 = LG_NLDS;
-    const ll N2 = ll(1) << lg2;
-    const int lg1 = lgN - lg2;
-    const int N1 = 1 << lg1;
-    const int C = NLDS >> lg1;  // columns per LDS tile
-    const int twsh = LG_TW - lgN;
-    // 1. column transforms (length N1) of the N1 x N2 row-major view, times
-    //    the twiddle w_N^{n2 k1}; rows stay in bit-reversed k1 order.
-    for (ll n20 = 0; n20 < N2; n20 += C) {
-        for (int t = tid; t < NLDS; t += WG) {
-            const int c = t % C, n1 = t / C;
-            const ll idx = (ll)n1 * N2 + n20 + c;
-            lds[c * N1 + n1] = make_double2(idx < n_in ? tilt_in(src[idx], beta, idx, tc) : 0.0, 0.0);
-        }
-        __syncthreads();
-        lds_dif(lds, lg1, C, twl);
-        for (int t = tid; t < NLDS; t += WG) {
-            const int c = t % C, p1 = t / C;
-            const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-            const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
-            scr[(ll)p1 * N2 + n2] = cmul(lds[c * N1 + p1], w);
-        }
-        __syncthreads();
-    }
-    // 2. per row: forward length-N2 transform, multiply by the kernel power
-    //    at frequency k1 + N1 k2, inverse transform.
-    for (int p1 = 0; p1 < N1; ++p1) {
-        const ll k1 = bitrev(p1, lg1);
-        double2 *row = scr + (ll)p1 * N2;
-        for (int t = tid; t < N2; t += WG) lds[t] = row[t];
-        __syncthreads();
-        lds_dif(lds, lg2, 1, twl);
-        for (int t = tid; t < N2; t += WG) {
-            const ll k2 = bitrev(t, lg2);
-            lds[t] = cmul(lds[t], kernel_power(q, k1 + (ll)N1 * k2, lgN, tw));
-        }
-        __syncthreads();
-        lds_dit_inv(lds, lg2, 1, twl);
-        for (int t = tid; t < N2; t += WG) row[t] = lds[t];
-        __syncthreads();
-    }
-    // 3. inverse column transforms after the conjugate twiddle; keep the window.
-    for (ll n20 = 0; n20 < N2; n20 += C) {
-        for (int t = tid; t < NLDS; t += WG) {
-            const int c = t % C, p1 = t / C;
-            const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-            const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
-            lds[c * N1 + p1] = cmulc(scr[(ll)p1 * N2 + n2], w);
-        }
-        __syncthreads();
-        lds_dit_inv(lds, lg1, C, twl);
-        for (int t = tid; t < NLDS; t += WG) {
-            const int c = t % C, n1 = t / C;
-            const ll idx = (ll)n1 * N2 + n20 + c;
-            if (idx >= out_off && idx < out_off + n_out)
-                dst[idx - out_off] = tilt_out(lds[c * N1 + n1].x * invN, beta, idx);
-        }
-        __syncthreads();
-    }
+    JobArgs u = a;
+    u.n_in = uni(a.n_in);
+    u.h = uni(a.h);
+    u.out_off = uni(a.out_off);
+    u.n_out = uni(a.n_out);
+    u.desc = __builtin_amdgcn_readfirstlane(a.desc);
+    u.lgN = __builtin_amdgcn_readfirstlane(a.lgN);
+    u.kind = __builtin_amdgcn_readfirstlane(a.kind);
+    u.ntile = __builtin_amdgcn_readfirstlane(a.ntile);
+    u.nph = __builtin_amdgcn_readfirstlane(a.nph);
+    return u;
 }
 
-__device__ __forceinline__ void count_conv(Stats *st, ll n_in, ll n_out)
+__device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 *lds, const double2 *__restrict__ tw,
+                                         const double2 *twl)
 {
-    if (threadIdx.x == 0 && st && n_out > 0) {
-        int l = ceil_log2(n_in);
-        st->convs += 1;
-        st->conv_in += n_in;
-        st->conv_out += n_out;
-        st->fft_points += ll(1) << (l < 1 ? 1 : l);
+    const int lgN = j.lgN;
+    const ll N = ll(1) << lgN;
+    const double invN = 1.0 / (double)N;
+    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const int tid = threadIdx.x;
+    for (int t = tid; t < N; t += WG)
+        lds[t] = make_double2(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0);
+    __syncthreads();
+    lds_dif(lds, lgN, 1, twl);
+    // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
+    for (ll f = tid; f <= N / 2; f += WG) {
+        const double2 m = kernel_power(q, f, lgN, tw);
+        const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
+        lds[t1] = cmul(lds[t1], m);
+        if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
     }
+    __syncthreads();
+    lds_dit_inv(lds, lgN, 1, twl);
+    for (ll t = tid; t < j.n_out; t += WG) j.dst[t] = tilt_out(lds[j.out_off + t].x * invN, j.beta, j.out_off + t);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2 *lds, const double2 *__restrict__ tw,
+                                             const double2 *twl)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int twsh = LG_TW - lgN;
+    const ll n20 = (ll)tile * C;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, n1 = t / C;
+        const ll idx = (ll)n1 * N2 + n20 + c;
+        lds[c * N1 + n1] = make_double2(idx < j.n_in ? tilt_in(j.src[idx], j.beta, idx, j.tc) : 0.0, 0.0);
+    }
+    __syncthreads();
+    lds_dif(lds, lg1, C, twl);
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, p1 = t / C;
+        const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
+        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        j.scr[(ll)p1 * N2 + n2] = cmul(lds[c * N1 + p1], w);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int tile, double2 *lds,
+                                          const double2 *__restrict__ tw, const double2 *twl)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1;
+    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const int tid = threadIdx.x;
+    const int p1 = tile;
+    const ll k1 = bitrev(p1, lg1);
+    double2 *row = j.scr + (ll)p1 * N2;
+    for (int t = tid; t < N2; t += WG) lds[t] = row[t];
+    __syncthreads();
+    lds_dif(lds, lg2, 1, twl);
+    for (int t = tid; t < N2; t += WG) {
+        const ll k2 = bitrev(t, lg2);
+        lds[t] = cmul(lds[t], kernel_power(q, k1 + (ll)N1 * k2, lgN, tw));
+    }
+    __syncthreads();
+    lds_dit_inv(lds, lg2, 1, twl);
+    for (int t = tid; t < N2; t += WG) row[t] = lds[t];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2 *lds, const double2 *__restrict__ tw,
+                                             const double2 *twl)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int twsh = LG_TW - lgN;
+    const double invN = 1.0 / (double)N;
+    const ll n20 = (ll)tile * C;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, p1 = t / C;
+        const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
+        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        lds[c * N1 + p1] = cmulc(j.scr[(ll)p1 * N2 + n2], w);
+    }
+    __syncthreads();
+    lds_dit_inv(lds, lg1, C, twl);
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, n1 = t / C;
+        const ll idx = (ll)n1 * N2 + n20 + c;
+        if (idx >= j.out_off && idx < j.out_off + j.n_out)
+            j.dst[idx - j.out_off] = tilt_out(lds[c * N1 + n1].x * invN, j.beta, idx);
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------ direct correlation
@@ -463,37 +505,28 @@ __device__ __forceinline__ void direct_wave(Mp p, const double *__restrict__ src
     }
 }
 
-#define DIRECT_MAX_H 160   // longest step count evaluated by direct stepping
-#define DIRECT_MAX_N 1024  // longest segment (64 lanes x 16 cells)
-
 __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 
-// Dispatch: direct stepping for short kernels, FFT correlation otherwise.
-__device__ __forceinline__ void correlate(Stats *st, const Mp &p, const double *__restrict__ src, ll n_in, ll h,
-                                          ll out_off, ll n_out, double *__restrict__ dst, double2 *scr,
-                                          double2 *lds, const double2 *__restrict__ tw, const double2 *twl,
-                                          double beta = 0.0, double tc = 0.0)
+// One tile of a job, executed by the whole workgroup (control flow uniform).
+__device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, int t, double2 *lds,
+                                         const double2 *__restrict__ tw, const double2 *twl)
 {
-    if (n_out <= 0) return;
-    const ll t0 = clk();
-    if (beta == 0.0 && h <= DIRECT_MAX_H && n_in <= DIRECT_MAX_N) {
+    if (j.kind == K_DIRECT) {
         if (threadIdx.x < 64) {
-            if (n_in <= 128) direct_wave<2>(p, src, n_in, h, out_off, n_out, dst);
-            else if (n_in <= 256) direct_wave<4>(p, src, n_in, h, out_off, n_out, dst);
-            else if (n_in <= 512) direct_wave<8>(p, src, n_in, h, out_off, n_out, dst);
-            else direct_wave<16>(p, src, n_in, h, out_off, n_out, dst);
+            if (j.n_in <= 128) direct_wave<2>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+            else if (j.n_in <= 256) direct_wave<4>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+            else if (j.n_in <= 512) direct_wave<8>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+            else direct_wave<16>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
         }
         __syncthreads();
-        if (threadIdx.x == 0 && st) {
-            st->n_direct += 1;
-            st->cyc_direct += clk() - t0;
-        }
-        return;
-    }
-    fft_correlate(p, src, n_in, h, out_off, n_out, dst, scr, lds, tw, twl, beta, tc);
-    if (threadIdx.x == 0 && st) {
-        st->n_fft += 1;
-        st->cyc_fft += clk() - t0;
+    } else if (j.kind == K_LDS) {
+        tile_lds(p, j, lds, tw, twl);
+    } else if (ph == 0) {
+        tile_col_fwd(j, t, lds, tw, twl);
+    } else if (ph == 1) {
+        tile_rows(p, j, t, lds, tw, twl);
+    } else {
+        tile_col_inv(j, t, lds, tw, twl);
     }
 }
 
@@ -728,6 +761,251 @@ __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const
     return fc;
 }
 
+// ---------------------------------------------------------------- work pool
+// The solve kernel is persistent.  Each workgroup claims the next option
+// (descriptors are sorted by decreasing cost) and drives it; once no option is
+// left it becomes a helper.  A driver publishes its correlations as jobs in its
+// own slots (slot 0: top level, slot s+1: recursion depth s); any workgroup
+// may claim a tile of a published job with one atomic add on the job's control
+// word.  A driver that needs a job's result claims the job's remaining tiles
+// itself, so a wait only ever depends on tiles that running workgroups have
+// claimed: the scheme cannot deadlock, whatever the number of resident
+// workgroups.  Every wait is bounded by a deadline as well; past it the launch
+// aborts and the options still in flight price NaN.
+//
+// Memory ordering (agent scope): a publisher's row data and job arguments are
+// released before the control word is stored; a claimer acquires after its
+// atomic add; a tile's writes are released before its completion is counted;
+// the workgroup that completes a phase opens the next one, or marks the job
+// done, with a release store, and the driver acquires before reading results.
+struct Job {
+    unsigned long long ctl;  // gen:16 | phase:8 | claimed:20 | total:20
+    unsigned done[3];        // completed tiles per phase
+    int pad;
+    JobArgs a;
+};
+static_assert(sizeof(Job) <= JOB_BYTES, "job slot");
+
+#define PH_DONE 0xFFu
+#define SLOT_TOP 0
+#define AGENT __HIP_MEMORY_SCOPE_AGENT
+
+__device__ __forceinline__ unsigned long long mkctl(unsigned gen, unsigned ph, unsigned claimed, unsigned total)
+{
+    return ((unsigned long long)(gen & 0xFFFFu) << 48) | ((unsigned long long)ph << 40) |
+           ((unsigned long long)claimed << 20) | (unsigned long long)total;
+}
+__device__ __forceinline__ unsigned ctl_ph(unsigned long long c) { return (unsigned)(c >> 40) & 0xFFu; }
+__device__ __forceinline__ unsigned ctl_claimed(unsigned long long c) { return (unsigned)(c >> 20) & 0xFFFFFu; }
+__device__ __forceinline__ unsigned ctl_total(unsigned long long c) { return (unsigned)c & 0xFFFFFu; }
+__device__ __forceinline__ unsigned ctl_gen(unsigned long long c) { return (unsigned)(c >> 48); }
+
+struct Pool {
+    PoolHdr *hdr;
+    unsigned long long *summary;  // bit w: workgroup w has a flagged slot (maintained loosely)
+    unsigned long long *bits;     // [n_wg]: bit s of word w = slot s of workgroup w has claimable tiles
+    Job *jobs;                    // [n_wg * JPW]
+    int n_wg;
+};
+
+// Shared control words are only ever read with atomic read-modify-writes:
+// those are performed at the device's coherence point, whereas a plain or
+// relaxed load may keep returning a line cached before another XCD wrote it.
+__device__ __forceinline__ unsigned long long rmw_read(unsigned long long *p)
+{
+    return __hip_atomic_fetch_or(p, 0ull, __ATOMIC_RELAXED, AGENT);
+}
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ ll now_ticks() { return (ll)__builtin_amdgcn_s_memrealtime(); }
+__device__ __forceinline__ bool aborted(const Pool &pl) { return (rmw_read((unsigned long long *)&pl.hdr->status) >> 32) != 0ull; }
+__device__ __forceinline__ void set_abort(const Pool &pl)
+{
+    __hip_atomic_fetch_or((unsigned long long *)&pl.hdr->status, 1ull << 32, __ATOMIC_RELAXED, AGENT);
+}
+
+// The summary bit of workgroup w may be stale in either direction; a helper
+// that finds it set over an empty word clears it, and whoever clears it
+// re-checks the word afterwards, so a set word never stays unannounced.
+__device__ __forceinline__ void summary_clear_recheck(const Pool &pl, int w)
+{
+    __hip_atomic_fetch_and(pl.summary + (w >> 6), ~(1ull << (w & 63)), __ATOMIC_SEQ_CST, AGENT);
+    if (__hip_atomic_fetch_or(pl.bits + w, 0ull, __ATOMIC_SEQ_CST, AGENT))
+        __hip_atomic_fetch_or(pl.summary + (w >> 6), 1ull << (w & 63), __ATOMIC_RELAXED, AGENT);
+}
+__device__ __forceinline__ void flag_slot(const Pool &pl, int ji)
+{
+    const int w = ji / JPW;
+    const unsigned long long old = __hip_atomic_fetch_or(pl.bits + w, 1ull << (ji % JPW), __ATOMIC_RELAXED, AGENT);
+    if (old == 0ull) __hip_atomic_fetch_or(pl.summary + (w >> 6), 1ull << (w & 63), __ATOMIC_RELAXED, AGENT);
+}
+__device__ __forceinline__ void unflag_slot(const Pool &pl, int ji)
+{
+    const int w = ji / JPW;
+    const unsigned long long bit = 1ull << (ji % JPW);
+    const unsigned long long old = __hip_atomic_fetch_and(pl.bits + w, ~bit, __ATOMIC_RELAXED, AGENT);
+    if ((old & ~bit) == 0ull) summary_clear_recheck(pl, w);
+}
+
+// Claim one tile of job ji (one lane).  True with *ph, *t set if the add
+// landed on an open phase with an unclaimed tile; the lane that takes the last
+// tile of a phase unflags the slot.
+__device__ __forceinline__ bool claim_tile(const Pool &pl, int ji, int *ph, int *t)
+{
+    Job *jb = pl.jobs + ji;
+    const unsigned long long c = __hip_atomic_fetch_add(&jb->ctl, 1ull << 20, __ATOMIC_RELAXED, AGENT);
+    const unsigned p = ctl_ph(c), k = ctl_claimed(c), tot = ctl_total(c);
+    if (p >= 3 || k >= tot) return false;
+    if (k + 1 == tot) unflag_slot(pl, ji);
+    fence_acq();
+    *ph = (int)p;
+    *t = (int)k;
+    return true;
+}
+
+// Count a finished tile (one lane, after the whole workgroup's writes) of a
+// job with nph phases of nt tiles; the lane that completes a phase opens the
+// next one or marks the job done.
+__device__ __forceinline__ void complete_tile(const Pool &pl, int ji, int ph, int nt, int nph)
+{
+    Job *jb = pl.jobs + ji;
+    const unsigned d = __hip_atomic_fetch_add(&jb->done[ph], 1u, __ATOMIC_ACQ_REL, AGENT);
+    if (d + 1 != (unsigned)nt) return;
+    const unsigned gen = ctl_gen(rmw_read(&jb->ctl));
+    if (ph + 1 < nph) {
+        __hip_atomic_exchange(&jb->ctl, mkctl(gen, ph + 1, 0, nt), __ATOMIC_RELEASE, AGENT);
+        flag_slot(pl, ji);
+    } else {
+        __hip_atomic_exchange(&jb->ctl, mkctl(gen, PH_DONE, 0, 0), __ATOMIC_RELEASE, AGENT);
+    }
+}
+
+// Copy a job's arguments into LDS (lanes 0..11 of wave 0, after the claim's acquire).
+__device__ __forceinline__ void fetch_args(const Pool &pl, int ji, JobArgs *sh)
+{
+    const int l = threadIdx.x;
+    if (l < (int)(sizeof(JobArgs) / 8)) {
+        unsigned long long *w = (unsigned long long *)&pl.jobs[ji].a;
+        ((unsigned long long *)sh)[l] = __hip_atomic_load(w + l, __ATOMIC_RELAXED, AGENT);
+    }
+}
+
+// Per-workgroup LDS state shared by the driver and helper roles.
+struct Shared {
+    int msg, ji, opt, pad;
+    JobArgs args;          // arguments of the tile a helper claimed
+    JobArgs jargs[JPW];    // arguments of each slot's pending job (driver)
+    int pub[JPW];          // slot state: 0 idle, 1 published job pending, 2 private job pending
+    unsigned gen[JPW];     // generation of the slot's last published job
+};
+
+// A helper: claim tiles of any published job until every option is done.
+// A claimed job's arguments must describe ranges inside its option's own
+// workspace area (rows, arena, FFT scratch); anything else is refused.
+__device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, const char *ws, const JobArgs &a, int ph,
+                                        int tile)
+{
+    if (a.desc < 0 || a.desc >= n || a.kind < K_DIRECT || a.kind > K_4STEP || a.lgN < 1 || a.lgN > LG_TW ||
+        ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN))
+        return false;
+    const Desc d = descs[a.desc];
+    if (d.model < 0) return false;
+    const char *lo = ws + d.ws_off;
+    const char *hi = lo + 8 * (2 * d.row_len + d.arena_len) + 16 * d.scr_len;
+    const char *s0 = (const char *)a.src, *s1 = (const char *)(a.src + a.n_in);
+    const char *d0 = (const char *)a.dst, *d1 = (const char *)(a.dst + a.n_out);
+    if (s0 < lo || s1 > hi || d0 < lo || d1 > hi) return false;
+    if (a.kind == K_4STEP) {
+        const char *c0 = (const char *)a.scr, *c1 = (const char *)(a.scr + (ll(1) << a.lgN));
+        if (c0 < lo || c1 > hi || a.lgN <= LG_NLDS) return false;
+    }
+    return true;
+}
+
+// A helper leaves once every option is done, the launch aborted, or it has
+// found nothing to claim for `idle_ticks` (helpers are never needed for
+// progress: drivers finish their own jobs).
+__device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs, const char *ws, Shared *sh,
+                            double2 *lds, const double2 *__restrict__ tw, const double2 *twl, ll idle_ticks)
+{
+    ll last_work = now_ticks();
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int nsum = (pl.n_wg + 63) >> 6;
+    const ll t_start = clk();
+    ll busy = 0, tiles = 0;
+    unsigned rot = blockIdx.x * 37u;
+    for (;;) {
+        if (tid < 64) {
+            int msg = 0, ji = -1;  // 0 nothing, 1 tile, 2 exit
+            unsigned long long st = 0ull, sw = 0ull;
+            if (l == 0) st = rmw_read((unsigned long long *)&pl.hdr->status);
+            if (l < nsum) sw = rmw_read(pl.summary + l);
+            st = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(st >> 32), 0) << 32) |
+                 (unsigned)__builtin_amdgcn_readlane((int)(unsigned)st, 0);
+            if ((ll)(st & 0xffffffffull) >= n || (st >> 32) || now_ticks() - last_work > idle_ticks) {
+                msg = 2;
+            } else {
+                const unsigned long long m = __ballot(sw != 0ull);
+                if (m) {
+                    // a workgroup with claimable work: rotate over summary words and bits
+                    const int r = (int)(rot & 63u);
+                    const unsigned long long rm = r ? ((m >> r) | (m << (64 - r))) : m;
+                    const int lane = (__ffsll((long long)rm) - 1 + r) & 63;
+                    int ok = 0, ph = 0, t = 0, cj = -1;
+                    if (l == lane) {
+                        const int r2 = (int)((rot >> 6) & 63u);
+                        const unsigned long long sr = r2 ? ((sw >> r2) | (sw << (64 - r2))) : sw;
+                        const int w = lane * 64 + ((__ffsll((long long)sr) - 1 + r2) & 63);
+                        const unsigned long long bw = (w < pl.n_wg) ? rmw_read(pl.bits + w) : 0ull;
+                        if (bw == 0ull) {
+                            if (w < pl.n_wg) summary_clear_recheck(pl, w);
+                        } else {
+                            cj = w * JPW + (63 - (int)__clzll(bw));  // deepest slot first
+                            ok = claim_tile(pl, cj, &ph, &t);
+                        }
+                    }
+                    ok = __builtin_amdgcn_readlane(ok, lane);
+                    if (ok) {
+                        msg = 1 | (__builtin_amdgcn_readlane(ph, lane) << 4) | (__builtin_amdgcn_readlane(t, lane) << 8);
+                        ji = __builtin_amdgcn_readlane(cj, lane);
+                    }
+                }
+                rot += 65u;
+                if (msg == 0) __builtin_amdgcn_s_sleep(2);
+            }
+            if ((msg & 15) == 1) fetch_args(pl, ji, &sh->args);
+            if (l == 0) {
+                sh->msg = msg;
+                sh->ji = ji;
+            }
+        }
+        __syncthreads();
+        const int msg = __builtin_amdgcn_readfirstlane(sh->msg);
+        const int ji = __builtin_amdgcn_readfirstlane(sh->ji);
+        const JobArgs a = uni_args(sh->args);
+        __syncthreads();
+        if ((msg & 15) == 2) break;
+        if ((msg & 15) != 1) continue;
+        const ll t0 = clk();
+        const int ph = (msg >> 4) & 15, tile = msg >> 8;
+        if (args_ok(descs, n, ws, a, ph, tile)) {
+            const Mp p = make_mp(descs[a.desc]);
+            run_tile(p, a, ph, tile, lds, tw, twl);
+        } else if (tid == 0) {
+            set_abort(pl);
+        }
+        if (tid == 0) complete_tile(pl, ji, ph, a.ntile, a.nph);
+        busy += clk() - t0;
+        ++tiles;
+        last_work = now_ticks();
+    }
+    if (tid == 0) {
+        __hip_atomic_fetch_add(&pl.hdr->helper_tiles, tiles, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_fetch_add(&pl.hdr->helper_busy, busy, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_fetch_add(&pl.hdr->helper_idle, clk() - t_start - busy, __ATOMIC_RELAXED, AGENT);
+    }
+}
+
 // ---------------------------------------------------------- the recursion
 struct Frame {
     ll r0;    // row i0 (lattices) / step n (BSM)
@@ -735,22 +1013,28 @@ struct Frame {
     ll h;     // trapezoid height
     ll b;     // last red column of row r0 (lattices)
     ll aoff;  // arena offset (doubles) of this frame's middle-row buffer
-    ll ret1;  // boundary returned by the first sub-trapezoid
+    ll soff;  // FFT scratch offset (complex) of this frame's correlation
     double *src, *dst, *mid;
     int stage, pad;
 };
 
 struct Ctx {
     Mp p;
-    Stats *st;  // work counters in LDS (updated by lane 0 only)
+    int desc;         // descriptor index of the option
+    Stats *st;        // work counters in LDS (updated by lane 0 only)
     double *lo, *hi;  // this option's workspace (doubles) for range checks
     double *arena;
     ll arena_len;
     double2 *scr;
+    ll scr_len;
     double2 *lds;
     const double2 *tw;
     const double2 *twl;
     ll *bnd;
+    Pool pl;
+    Tune tn;
+    Shared *sh;
+    int *err_sh;
 };
 
 __device__ __forceinline__ bool in_ws(const Ctx &cx, const double *p, ll first, ll last)
@@ -759,11 +1043,195 @@ __device__ __forceinline__ bool in_ws(const Ctx &cx, const double *p, ll first, 
     return (p + first >= cx.lo) && (p + last < cx.hi);
 }
 
+__device__ __forceinline__ void count_conv(Stats *st, ll n_in, ll n_out)
+{
+    if (threadIdx.x == 0 && st && n_out > 0) {
+        int l = ceil_log2(n_in);
+        st->convs += 1;
+        st->conv_in += n_in;
+        st->conv_out += n_out;
+        st->fft_points += ll(1) << (l < 1 ? 1 : l);
+    }
+}
+
+__device__ __forceinline__ void set_err(const Ctx &cx, int e)
+{
+    if (threadIdx.x == 0 && *cx.err_sh == 0) *cx.err_sh = e;
+}
+
+// Correlate src[0..n_in) with the h-step kernel and write the window
+// [out_off, out_off + n_out) to dst (see the job description above), as the
+// pending job of slot `slot`, using the FFT scratch from offset soff.  Large
+// jobs are published to the pool; the others stay private to the driver.
+// Either way the work is done (or finished) by conv_wait.  Returns the scratch
+// (complex elements) the job holds until then.
+__device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, const double *src, ll n_in, ll h,
+                                          ll out_off, ll n_out, double *dst, double beta = 0.0, double tc = 0.0)
+{
+    if (n_out <= 0) return 0;
+    count_conv(cx.st, n_in, n_out);
+    JobArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.n_in = n_in;
+    a.h = h;
+    a.out_off = out_off;
+    a.n_out = n_out;
+    a.beta = beta;
+    a.tc = tc;
+    a.desc = cx.desc;
+    a.pad = 0;
+    int lgN = ceil_log2(n_in);
+    if (lgN < 1) lgN = 1;
+    a.lgN = lgN;
+    const bool direct = beta == 0.0 && h <= cx.tn.direct_max_h && n_in <= cx.tn.direct_max_n;
+    a.kind = direct ? K_DIRECT : (lgN <= LG_NLDS ? K_LDS : K_4STEP);
+    a.nph = a.kind == K_4STEP ? 3 : 1;
+    a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
+    const ll need = a.kind == K_4STEP ? (ll(1) << lgN) : 0;
+    a.scr = cx.scr + soff;
+    if (soff + need > cx.scr_len || lgN > LG_TW || slot >= JPW) {
+        set_err(cx, DEV_ARENA);
+        return 0;
+    }
+    const bool publish = cx.pl.n_wg > 1 && (direct ? cx.tn.pub_direct != 0 : lgN >= cx.tn.pub_min_lg);
+    if (publish) __syncthreads();  // the workgroup's writes of the input row precede the release below
+    if (threadIdx.x == 0) {
+        if (direct) cx.st->n_direct += 1;
+        else cx.st->n_fft += 1;
+        cx.sh->jargs[slot] = a;
+        cx.sh->pub[slot] = publish ? 1 : 2;
+        if (publish) {
+            const int ji = blockIdx.x * JPW + slot;
+            Job *jb = cx.pl.jobs + ji;
+            jb->a = a;
+            for (int k = 0; k < 3; ++k) __hip_atomic_exchange(&jb->done[k], 0u, __ATOMIC_RELAXED, AGENT);
+            const unsigned gen = cx.sh->gen[slot] + 1;
+            cx.sh->gen[slot] = gen;
+            __hip_atomic_exchange(&jb->ctl, mkctl(gen, 0, 0, a.ntile), __ATOMIC_RELEASE, AGENT);
+            flag_slot(cx.pl, ji);
+            cx.st->n_published += 1;
+        }
+    }
+    __syncthreads();
+    return need;
+}
+
+// Finish the pending job of `slot`: a private job's tiles are computed here
+// in order; for a published one the driver takes the tiles no other
+// workgroup has claimed and waits for the rest.
+__device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
+{
+    const int mode = __builtin_amdgcn_readfirstlane(cx.sh->pub[slot]);
+    if (mode == 0) return;
+    const JobArgs a = uni_args(cx.sh->jargs[slot]);
+    const int ji = blockIdx.x * JPW + slot;
+    Job *jb = cx.pl.jobs + ji;
+    const ll t0 = clk();
+    const ll deadline = now_ticks() + cx.tn.timeout_ticks;
+    ll work = 0;
+    int nph = 0, nt = 0;  // private: next tile
+    for (;;) {
+        int msg;  // 1 done, 2 tile (phase, index), 3 abort, 0 nothing yet
+        if (mode == 2) {
+            msg = (nph < a.nph) ? (2 | (nph << 4) | (nt << 8)) : 1;
+            if (++nt == a.ntile) {
+                nt = 0;
+                ++nph;
+            }
+        } else {
+            if (threadIdx.x < 64) {
+                int m = 0, ph = 0, t = 0;
+                if (threadIdx.x == 0) {
+                    const unsigned long long c = rmw_read(&jb->ctl);
+                    const unsigned p = ctl_ph(c);
+                    if (p == PH_DONE) {
+                        fence_acq();
+                        m = 1;
+                    } else if (p < 3 && ctl_claimed(c) < ctl_total(c) && claim_tile(cx.pl, ji, &ph, &t)) {
+                        m = 2 | (ph << 4) | (t << 8);
+                    } else if (aborted(cx.pl) || now_ticks() > deadline) {
+                        set_abort(cx.pl);
+                        m = 3;
+                    } else {
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    cx.sh->msg = m;
+                }
+            }
+            __syncthreads();
+            msg = __builtin_amdgcn_readfirstlane(cx.sh->msg);
+            __syncthreads();
+        }
+        if ((msg & 15) == 1) break;
+        if ((msg & 15) == 3) {
+            set_err(cx, DEV_TIMEOUT);
+            break;
+        }
+        if ((msg & 15) == 2) {
+            const ll tb = clk();
+            run_tile(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl);
+            if (mode == 1 && threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
+            work += clk() - tb;
+        }
+    }
+    if (threadIdx.x == 0) {
+        cx.sh->pub[slot] = 0;
+        cx.st->cyc_tiles += work;
+        cx.st->cyc_wait += clk() - t0 - work;
+    }
+    __syncthreads();
+}
+
+// After an error: retire every pending job of this workgroup without computing
+// it (published ones by claiming and completing their remaining tiles, so
+// that no other workgroup still works on the slot when it is reused).
+__device__ __forceinline__ void drain(const Ctx &cx)
+{
+    if (threadIdx.x == 0) {
+        const ll deadline = now_ticks() + cx.tn.timeout_ticks;
+        for (int slot = 0; slot < JPW; ++slot) {
+            if (cx.sh->pub[slot] == 1) {
+                const int ji = blockIdx.x * JPW + slot;
+                Job *jb = cx.pl.jobs + ji;
+                const JobArgs &a = cx.sh->jargs[slot];
+                for (;;) {
+                    const unsigned long long c = rmw_read(&jb->ctl);
+                    const unsigned p = ctl_ph(c);
+                    int ph, t;
+                    if (p == PH_DONE) break;
+                    if (p < 3 && ctl_claimed(c) < ctl_total(c) && claim_tile(cx.pl, ji, &ph, &t)) {
+                        complete_tile(cx.pl, ji, ph, a.ntile, a.nph);
+                    } else if (aborted(cx.pl) || now_ticks() > deadline) {
+                        set_abort(cx.pl);
+                        break;
+                    } else {
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+            }
+            cx.sh->pub[slot] = 0;
+        }
+    }
+    __syncthreads();
+}
+
+// Read one double a pool job wrote (after conv_wait's acquire), as a vector load.
+__device__ __forceinline__ double read_result(const double *p)
+{
+    unsigned long long v = __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, AGENT);
+    return __longlong_as_double((long long)v);
+}
+
 // Solve one trapezoid (model-dependent geometry, see the frame stages below)
 // and return the boundary of its last row.  All lanes call it; control flow is
-// uniform.  On a failed range check the error is stored in *err.
+// uniform.  A frame at depth s keeps its correlations in job slot s + 1: the
+// first one is computed while the first sub-trapezoid is solved, the second
+// while the second is, and the frame ends only after both are done.  Each
+// iteration first finishes the frame's pending correlation (stages 1 and 2),
+// then takes the frame one stage further, which may submit one correlation.
 __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh, ll *ret_sh,
-                              int *err_sh, ll *leaf_sh)
+                                              ll *leaf_sh)
 {
     const Mp d = cx.p;
     const int tid = threadIdx.x;
@@ -775,19 +1243,27 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
     __syncthreads();
     for (;;) {
         const int s = *sp_sh;
-        if (s < 0 || *err_sh) break;
+        if (s < 0 || *cx.err_sh) break;
         Frame fr = stk[s];
         fr.r0 = uni(fr.r0);
         fr.c0 = uni(fr.c0);
         fr.h = uni(fr.h);
         fr.b = uni(fr.b);
         fr.aoff = uni(fr.aoff);
+        fr.soff = uni(fr.soff);
+        fr.stage = __builtin_amdgcn_readfirstlane(fr.stage);
+        const int slot = s + 1;
         const ll rv = uni(*ret_sh);
         __syncthreads();
-        bool pop = false;
+        if (fr.stage > 0) conv_wait(cx, slot);
+        bool pop = false, leaf = false;
         ll result = 0;
         Frame child;
         int e = DEV_OK;
+        // the correlation this step submits, if any
+        const double *csrc = nullptr;
+        double *cdst = nullptr;
+        ll cn = 0, ch = 0, coff = 0, cout = 0;
         if (d.model != BSM) {
             // Lattice trapezoid (i0 = r0): red cells [c0, b] of row i0 in src;
             // produces the red cells of row i0 - h in dst.
@@ -796,33 +1272,21 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
                 if (nred <= BAND) {
-                    if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) {
-                        e = DEV_RANGE;
-                    } else {
-                        const ll tb = clk();
-                        if (tid < 64) {
-                            const ll r = (d.model == BINOMIAL)
-                                             ? band_bin(d, i0, c0, h, b, fr.src, fr.dst, cx.bnd, nullptr)
-                                             : band_tri(d, i0, c0, h, b, fr.src, fr.dst, cx.bnd, nullptr);
-                            if (tid == 0) {
-                                *leaf_sh = r;
-                                cx.st->band_rows += h;
-                                cx.st->cyc_band += clk() - tb;
-                            }
-                        }
-                        __syncthreads();
-                        result = *leaf_sh;
-                    }
+                    if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) e = DEV_RANGE;
+                    else leaf = true;
                     pop = true;
                 } else {
-                    // (1) row r = i0 - h1, columns [c0, b - span h1], by FFT from row i0.
+                    // (1) row r = i0 - h1, columns [c0, b - span h1], by correlation from row i0.
                     double *mid = cx.arena + fr.aoff - c0;
-                    if (fr.aoff + nred > cx.arena_len) e = DEV_ARENA;
+                    if (fr.aoff + nred > cx.arena_len || slot >= JPW) e = DEV_ARENA;
                     else if (!in_ws(cx, fr.src, c0, b)) e = DEV_RANGE;
                     else {
-                        count_conv(cx.st, nred, nred - span * h1);
-                        correlate(cx.st, d, fr.src + c0, nred, h1, (span == 1) ? 0 : h1, nred - span * h1,
-                                      mid + c0, cx.scr, cx.lds, cx.tw, cx.twl);
+                        csrc = fr.src + c0;
+                        cn = nred;
+                        ch = h1;
+                        coff = (span == 1) ? 0 : h1;
+                        cout = nred - span * h1;
+                        cdst = mid + c0;
                         fr.mid = mid;
                         fr.stage = 1;
                         // (2) sub-trapezoid on the last span*h1 red cells of row i0
@@ -830,20 +1294,21 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                     }
                 }
             } else if (fr.stage == 1) {
-                // (3) row i0 - h, columns [c0, br - span h2], by FFT from row r.
+                // (3) row i0 - h, columns [c0, br - span h2], by correlation from row r.
                 const ll br = rv;
                 const ll n2 = br - c0 + 1;
                 if (!in_ws(cx, fr.mid, c0, br) || !in_ws(cx, fr.dst, c0, br)) e = DEV_RANGE;
                 else {
-                    count_conv(cx.st, n2, n2 - span * h2);
-                    if (n2 - span * h2 > 0)
-                        correlate(cx.st, d, fr.mid + c0, n2, h2, (span == 1) ? 0 : h2, n2 - span * h2,
-                                      fr.dst + c0, cx.scr, cx.lds, cx.tw, cx.twl);
-                    fr.ret1 = br;
+                    csrc = fr.mid + c0;
+                    cn = n2;
+                    ch = h2;
+                    coff = (span == 1) ? 0 : h2;
+                    cout = n2 - span * h2;
+                    cdst = fr.dst + c0;
                     fr.stage = 2;
                     // (4) sub-trapezoid on the last span*h2 red cells of row r
-                    child = Frame{i0 - h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst,
-                                  nullptr, 0, 0};
+                    child = Frame{i0 - h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst, nullptr,
+                                  0, 0};
                 }
             } else {
                 result = rv;
@@ -857,33 +1322,23 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll h1 = h / 2, h2 = h - h1;
             if (fr.stage == 0) {
                 if (h <= (BAND - 2) / 2) {
-                    if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) {
-                        e = DEV_RANGE;
-                    } else {
-                        const ll tb = clk();
-                        if (tid < 64) {
-                            const ll r = band_bsm(d, n, f, h, f + 2 * h, fr.src, fr.dst, cx.bnd, nullptr);
-                            if (tid == 0) {
-                                *leaf_sh = r;
-                                cx.st->band_rows += h;
-                                cx.st->cyc_band += clk() - tb;
-                            }
-                        }
-                        __syncthreads();
-                        result = *leaf_sh;
-                    }
+                    if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) e = DEV_RANGE;
+                    else leaf = true;
                     pop = true;
                 } else {
                     // middle step n+h1 on [f-h1+1, f+h+h2] (2h cells)
                     const ll base = f - h1 + 1;
                     double *mid = cx.arena + fr.aoff - base;
-                    if (fr.aoff + 2 * h > cx.arena_len) e = DEV_ARENA;
+                    if (fr.aoff + 2 * h > cx.arena_len || slot >= JPW) e = DEV_ARENA;
                     else if (!in_ws(cx, fr.src, f + 1, f + 2 * h)) e = DEV_RANGE;
                     else {
                         // conv 1: red cells [f+1, f+2h] -> [f+1+h1, f+2h-h1] of step n+h1
-                        count_conv(cx.st, 2 * h, 2 * h - 2 * h1);
-                        correlate(cx.st, d, fr.src + f + 1, 2 * h, h1, h1, 2 * h - 2 * h1, mid + f + 1 + h1,
-                                      cx.scr, cx.lds, cx.tw, cx.twl);
+                        csrc = fr.src + f + 1;
+                        cn = 2 * h;
+                        ch = h1;
+                        coff = h1;
+                        cout = 2 * h - 2 * h1;
+                        cdst = mid + f + 1 + h1;
                         fr.mid = mid;
                         fr.stage = 1;
                         child = Frame{n, f, h1, 0, fr.aoff + 2 * h, 0, fr.src, mid, nullptr, 0, 0};
@@ -896,10 +1351,12 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                 else if (!in_ws(cx, fr.mid, fp + 1, f + h + h2) || !in_ws(cx, fr.dst, fp + 1 + h2, f + h)) e = DEV_RANGE;
                 else {
                     // conv 2: red cells [f'+1, f+h+h2] of step n+h1 -> [f'+1+h2, f+h] of step n+h
-                    count_conv(cx.st, nin, nin - 2 * h2);
-                    correlate(cx.st, d, fr.mid + fp + 1, nin, h2, h2, nin - 2 * h2, fr.dst + fp + 1 + h2,
-                                  cx.scr, cx.lds, cx.tw, cx.twl);
-                    fr.ret1 = fp;
+                    csrc = fr.mid + fp + 1;
+                    cn = nin;
+                    ch = h2;
+                    coff = h2;
+                    cout = nin - 2 * h2;
+                    cdst = fr.dst + fp + 1 + h2;
                     fr.stage = 2;
                     child = Frame{n + h1, fp, h2, 0, fr.aoff + 2 * h, 0, fr.mid, fr.dst, nullptr, 0, 0};
                 }
@@ -908,14 +1365,34 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                 pop = true;
             }
         }
+        if (leaf) {
+            const ll tb = clk();
+            if (tid < 64) {
+                ll r;
+                if (d.model == BINOMIAL) r = band_bin(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
+                else if (d.model == TRINOMIAL) r = band_tri(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
+                else r = band_bsm(d, fr.r0, fr.c0, fr.h, fr.c0 + 2 * fr.h, fr.src, fr.dst, cx.bnd, nullptr);
+                if (tid == 0) {
+                    *leaf_sh = r;
+                    cx.st->band_rows += fr.h;
+                    cx.st->cyc_band += clk() - tb;
+                }
+            }
+            __syncthreads();
+            result = *leaf_sh;
+        }
+        if (e == DEV_OK && !pop && cout > 0)
+            child.soff = fr.soff + conv_submit(cx, slot, fr.soff, csrc, cn, ch, coff, cout, cdst);
+        else if (!pop)
+            child.soff = fr.soff;
         if (tid == 0) {
             if (e != DEV_OK) {
-                *err_sh = e;
+                if (*cx.err_sh == 0) *cx.err_sh = e;
             } else if (pop) {
                 *ret_sh = result;
                 *sp_sh = s - 1;
             } else if (s + 1 >= MAXD) {
-                *err_sh = DEV_STACK;
+                *cx.err_sh = DEV_STACK;
             } else {
                 stk[s] = fr;
                 stk[s + 1] = child;
@@ -932,7 +1409,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
 
 // --------------------------------------------------------------- drivers
 __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
-                                ll *ret_sh, int *err_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
+                                                ll *ret_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
     const Mp d = cx.p;
     const ll T = d.T;
@@ -991,8 +1468,9 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         if (cx.bnd)
             for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = bin ? i : 2 * i;
         const ll hh = T - 1;
-        count_conv(cx.st, b + 1, 1);
-        correlate(cx.st, d, src, b + 1, hh, bin ? 0 : hh, 1, val_sh, cx.scr, cx.lds, cx.tw, cx.twl, beta, tc);
+        conv_submit(cx, SLOT_TOP, 0, src, b + 1, hh, bin ? 0 : hh, 1, dst, beta, tc);
+        conv_wait(cx, SLOT_TOP);
+        if (tid == 0) *val_sh = read_result(dst);
         __syncthreads();
         return *val_sh;
     }
@@ -1021,20 +1499,20 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         if (h > i0) h = i0;
         Frame root{i0, 0, h, b, 0, 0, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        b = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, err_sh, leaf_sh);
-        if (*err_sh) return NAN;
+        b = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        if (*cx.err_sh) return NAN;
         i0 -= h;
         double *t = src;
         src = dst;
         dst = t;
     }
-    const double p = (b >= 0) ? src[0] : d.S - d.K;
+    const double p = (b >= 0) ? read_result(src) : d.S - d.K;
     __syncthreads();
     return p;
 }
 
 __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
-                            ll *ret_sh, int *err_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
+                                            ll *ret_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
     const Mp d = cx.p;
     const ll T = d.T;
@@ -1069,7 +1547,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
     double *src = A, *dst = B;
     for (;;) {
         if (n == T) {
-            const double v = (f >= 0) ? ex_bsm(d, 0) : src[0];
+            const double v = (f >= 0) ? ex_bsm(d, 0) : read_result(src);
             __syncthreads();
             return d.K * v;
         }
@@ -1077,8 +1555,9 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
             if (cx.bnd)
                 for (ll m = n + 1 + tid; m <= T; m += WG) cx.bnd[m] = NONE;
             const ll hh = T - n;
-            count_conv(cx.st, R - L + 1, 1);
-            correlate(cx.st, d, src + L, R - L + 1, hh, hh, 1, val_sh, cx.scr, cx.lds, cx.tw, cx.twl);
+            conv_submit(cx, SLOT_TOP, 0, src + L, R - L + 1, hh, hh, 1, dst);
+            conv_wait(cx, SLOT_TOP);
+            if (tid == 0) *val_sh = read_result(dst);
             __syncthreads();
             return d.K * (*val_sh);
         }
@@ -1101,13 +1580,14 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
         }
         ll h = w / 2;
         if (h > T - n) h = T - n;
-        Frame root{n, f, h, 0, 0, 0, src, dst, nullptr, 0, 0};
+        // the rest of step n+h, red cells [f+1+h, R-h] from [f+1, R] of step n,
+        // is computed while the trapezoid is solved
+        const ll need = conv_submit(cx, SLOT_TOP, 0, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h);
+        Frame root{n, f, h, 0, 0, need, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        const ll fn = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, err_sh, leaf_sh);
-        if (*err_sh) return NAN;
-        // the rest of step n+h: red cells [f+1+h, R-h] from [f+1, R] of step n
-        count_conv(cx.st, w, w - 2 * h);
-        correlate(cx.st, d, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h, cx.scr, cx.lds, cx.tw, cx.twl);
+        const ll fn = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        conv_wait(cx, SLOT_TOP);
+        if (*cx.err_sh) return NAN;
         n += h;
         R -= h;
         L += h;
@@ -1118,9 +1598,67 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
     }
 }
 
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) solve_kernel(const Desc *__restrict__ descs, char *ws,
-                                                   const double2 *__restrict__ tw, double *price,
-                                                   ll *bnd, ll bnd_stride, int32_t *err, Stats *stats)
+// Drive one option (descriptor index o) to its price, with the whole workgroup.
+__device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, const double2 *__restrict__ tw,
+                                             double *price, ll *bnd, ll bnd_stride, int32_t *err, Stats *stats,
+                                             const Pool &pl, const Tune &tn, double2 *lds, const double2 *twl,
+                                             Frame *stk, int *sp_sh, int *err_sh, ll *ret_sh, ll *leaf_sh,
+                                             ll *red_sh, double *val_sh, Stats *st_sh, Shared *sh)
+{
+    const int tid = threadIdx.x;
+    char *base = ws + d.ws_off;
+    double *rowA = (double *)base;
+    double *rowB = rowA + d.row_len;
+    double *arena = rowB + d.row_len;
+    double2 *scr = (double2 *)(arena + d.arena_len);
+    Ctx cx;
+    cx.p = make_mp(d);
+    cx.desc = (int)o;
+    cx.lo = rowA;
+    cx.hi = (double *)(scr + d.scr_len);
+    cx.arena = arena;
+    cx.arena_len = d.arena_len;
+    cx.scr = scr;
+    cx.scr_len = d.scr_len;
+    cx.lds = lds;
+    cx.tw = tw;
+    cx.twl = twl;
+    cx.bnd = bnd ? bnd + d.out_index * bnd_stride : nullptr;
+    cx.st = st_sh;
+    cx.pl = pl;
+    cx.tn = tn;
+    cx.sh = sh;
+    cx.err_sh = err_sh;
+    if (tid == 0) {
+        *err_sh = 0;
+        *ret_sh = 0;
+        *st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __syncthreads();
+    const ll ttot = clk();
+    double p;
+    if (d.model == BSM) p = drive_bsm(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
+    else p = drive_lattice(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
+    __syncthreads();
+    if (*err_sh) drain(cx);
+    if (tid == 0) {
+        // a refused job or an expired wait anywhere in the launch: nothing
+        // finished after it is trusted
+        if (!*err_sh && aborted(pl)) *err_sh = DEV_ABORT;
+        price[d.out_index] = *err_sh ? NAN : p;
+        if (err) err[d.out_index] = *err_sh;
+        st_sh->cyc_total = clk() - ttot;
+        stats[d.out_index] = *st_sh;
+        __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
+    }
+}
+
+// Persistent solve kernel: options first (one driver workgroup each, claimed
+// in descriptor order), then helping with the published jobs of the drivers
+// still running.
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
+solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__restrict__ tw, double *price, ll *bnd,
+             ll bnd_stride, int32_t *err, Stats *stats, Pool pl, Tune tn)
 {
     __shared__ double2 lds[NLDS];
     __shared__ double2 twl[NLDS / 2];
@@ -1129,52 +1667,45 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
     __shared__ ll ret_sh, leaf_sh, red_sh[WG / 64];
     __shared__ double val_sh;
     __shared__ Stats st_sh;
+    __shared__ Shared sh;
 
-    const Desc d = descs[blockIdx.x];
-    if (d.model < 0) {  // rejected on the host: no work, price NaN
-        if (threadIdx.x == 0) {
-            price[d.out_index] = NAN;
-            stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NLDS / 2; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS)];
+    for (int t = tid; t < JPW; t += WG) {
+        sh.pub[t] = 0;
+        sh.gen[t] = 0;
+    }
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) sh.opt = (int)__hip_atomic_fetch_add(&pl.hdr->next_option, 1u, __ATOMIC_RELAXED, AGENT);
+        __syncthreads();
+        const ll o = __builtin_amdgcn_readfirstlane(sh.opt);
+        __syncthreads();
+        if (o >= n) break;
+        const Desc d = descs[o];
+        if (d.model < 0) {  // rejected on the host: no work, price NaN
+            if (tid == 0) {
+                price[d.out_index] = NAN;
+                stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
+            }
+        } else {
+            drive_option(d, o, ws, tw, price, bnd, bnd_stride, err, stats, pl, tn, lds, twl, stk, &sp_sh, &err_sh,
+                         &ret_sh, &leaf_sh, red_sh, &val_sh, &st_sh, &sh);
         }
-        return;
+        __syncthreads();
     }
-    char *base = ws + d.ws_off;
-    double *rowA = (double *)base;
-    double *rowB = rowA + d.row_len;
-    double *arena = rowB + d.row_len;
-    double2 *scr = (double2 *)(arena + d.arena_len);
-    Ctx cx;
-    cx.p = make_mp(d);
-    cx.lo = rowA;
-    cx.hi = (double *)(scr + d.nfft);
-    cx.arena = arena;
-    cx.arena_len = d.arena_len;
-    cx.scr = scr;
-    cx.lds = lds;
-    cx.tw = tw;
-    cx.twl = twl;
-    for (int t = threadIdx.x; t < NLDS / 2; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS)];
-    cx.bnd = bnd ? bnd + d.out_index * bnd_stride : nullptr;
-    cx.st = &st_sh;
-    if (threadIdx.x == 0) {
-        err_sh = 0;
-        ret_sh = 0;
-        st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    }
-    __syncthreads();
-    const ll ttot = clk();
-    double p;
-    if (d.model == BSM)
-        p = drive_bsm(cx, rowA, rowB, stk, &sp_sh, &ret_sh, &err_sh, &leaf_sh, red_sh, &val_sh);
-    else
-        p = drive_lattice(cx, rowA, rowB, stk, &sp_sh, &ret_sh, &err_sh, &leaf_sh, red_sh, &val_sh);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        price[d.out_index] = err_sh ? NAN : p;
-        if (err) err[d.out_index] = err_sh;
-        st_sh.cyc_total = clk() - ttot;
-        stats[d.out_index] = st_sh;
-    }
+    helper_loop(pl, n, descs, ws, &sh, lds, tw, twl, tn.idle_ticks);
+}
+
+// Clears the pool header, the summary bitmap and the slot words before a launch.
+__global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsigned long long *bits, int n_wg)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 16) ((int64_t *)hdr)[t] = 0;
+    if (t == 0) hdr->n_wg = (uint32_t)n_wg;
+    if (t < MAX_WG / 64) summary[t] = 0ull;
+    if (t < n_wg) bits[t] = 0ull;
 }
 
 __global__ void twiddle_kernel(double2 *tw)
@@ -1194,13 +1725,24 @@ int launch_twiddles(void *d_tw, void *stream)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
-int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price,
-                 int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, void *stream)
+int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price, int64_t *d_bnd,
+                 int64_t bnd_stride, int32_t *d_err, const Tune &tune, void *stream)
 {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(solve_kernel, dim3((unsigned)n), dim3(WG), 0, (hipStream_t)stream, d_desc, d_ws,
+    int n_wg = tune.workgroups;
+    if (n_wg < 1 || n_wg > MAX_WG) return 1;
+    char *pool = d_ws + pool_offset(n);
+    Pool pl;
+    pl.hdr = (PoolHdr *)pool;
+    pl.summary = (unsigned long long *)(pool + POOL_SUMMARY);
+    pl.bits = (unsigned long long *)(pool + POOL_BITS);
+    pl.jobs = (Job *)(pool + POOL_JOBS);
+    pl.n_wg = n_wg;
+    hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((MAX_WG + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       pl.hdr, pl.summary, pl.bits, n_wg);
+    hipLaunchKernelGGL(solve_kernel, dim3((unsigned)n_wg), dim3(WG), 0, (hipStream_t)stream, d_desc, (ll)n, d_ws,
                        (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err,
-                       (Stats *)(d_ws + stats_offset(n)));
+                       (Stats *)(d_ws + stats_offset(n)), pl, tune);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

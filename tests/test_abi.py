@@ -60,4 +60,6 @@ def test_workspace_bytes_grow_with_T():
     assert 0 < a < b
     # invalid options take no workspace
     bad = [dict(inputs.CONFIG1, S0=-1.0)]
-    assert binding.workspace_bytes(bad) <= 1024  # descriptor + counters only
+    # descriptor, counters and the work pool of the persistent kernel only
+    assert binding.workspace_bytes(bad) == binding.workspace_bytes([])
+    assert binding.workspace_bytes([]) <= 9 * 2**20
