@@ -169,7 +169,7 @@ size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambd
     for (int64_t i = 0; i < n; ++i) {
         Desc &d = tmp[(size_t)i];
         aop_status st = make_desc(opts[i], lambda, d);
-        if (st == AOP_OK && prec != AOP_FP64) st = AOP_ENOTIMPL;
+        if (st == AOP_OK && prec != AOP_FP64 && prec != AOP_MIXED) st = AOP_EINVAL;
         d.out_index = i;
         d.prec = prec;
         if (status) status[i] = st;
@@ -403,7 +403,7 @@ aop_status aop_price(aop_ctx *ctx, const aop_option *opt, int32_t precision, dou
     {
         Desc d;
         ost = make_desc(*opt, ctx->lambda, d);
-        if (ost == AOP_OK && precision != AOP_FP64) ost = AOP_ENOTIMPL;
+        if (ost == AOP_OK && precision != AOP_FP64 && precision != AOP_MIXED) ost = AOP_EINVAL;
         if (ost != AOP_OK) return (aop_status)ost;
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;

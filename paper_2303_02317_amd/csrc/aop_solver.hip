@@ -221,6 +221,180 @@ __device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl)
     }
 }
 
+// ------------------------------------------- split-precision (FP32 hi/lo)
+// The mixed-precision transforms hold every value as an unevaluated sum of
+// two FP32 numbers, hi + lo with |lo| <= ulp(hi)/2, and use error-free
+// transformations: two-sum for additions and the FMA-exact product for
+// multiplications, so each operation is exact up to a rounding of order
+// 2^-48 relative; all arithmetic is FP32.  Twiddles come split the same way.
+// Contraction is disabled inside these helpers: the two-sum identities need
+// every intermediate rounded exactly as written.
+struct CF {
+    float rh, rl, ih, il;  // real hi/lo, imaginary hi/lo
+};
+
+__device__ __forceinline__ void ff_two_sum(float a, float b, float &s, float &e)
+{
+#pragma clang fp contract(off)
+    s = a + b;
+    const float v = s - a;
+    e = (a - (s - v)) + (b - v);
+}
+__device__ __forceinline__ void ff_norm(float s, float e, float &h, float &l)
+{
+#pragma clang fp contract(off)
+    h = s + e;
+    l = e - (h - s);
+}
+__device__ __forceinline__ void ff_add(float ah, float al, float bh, float bl, float &h, float &l)
+{
+#pragma clang fp contract(off)
+    float s, e;
+    ff_two_sum(ah, bh, s, e);
+    e += al + bl;
+    ff_norm(s, e, h, l);
+}
+__device__ __forceinline__ CF cf_add(const CF &a, const CF &b)
+{
+    CF r;
+    ff_add(a.rh, a.rl, b.rh, b.rl, r.rh, r.rl);
+    ff_add(a.ih, a.il, b.ih, b.il, r.ih, r.il);
+    return r;
+}
+__device__ __forceinline__ CF cf_sub(const CF &a, const CF &b)
+{
+    CF r;
+    ff_add(a.rh, a.rl, -b.rh, -b.rl, r.rh, r.rl);
+    ff_add(a.ih, a.il, -b.ih, -b.il, r.ih, r.il);
+    return r;
+}
+// x*y + u*v for split operands, with sy = +1 or -1 on the second product.
+__device__ __forceinline__ void ff_dot2(float xh, float xl, float yh, float yl, float uh, float ul, float vh,
+                                        float vl, float sg, float &h, float &l)
+{
+#pragma clang fp contract(off)
+    const float p1 = xh * yh;
+    const float e1 = fmaf(xh, yh, -p1);
+    const float p2 = sg * (uh * vh);
+    const float e2 = sg * fmaf(uh, vh, -(uh * vh));
+    float s, e;
+    ff_two_sum(p1, p2, s, e);
+    e += (e1 + e2) + (fmaf(xh, yl, xl * yh) + sg * fmaf(uh, vl, ul * vh));
+    ff_norm(s, e, h, l);
+}
+__device__ __forceinline__ CF cf_mul(const CF &a, const CF &w)  // a * w
+{
+    CF r;
+    ff_dot2(a.rh, a.rl, w.rh, w.rl, a.ih, a.il, w.ih, w.il, -1.0f, r.rh, r.rl);
+    ff_dot2(a.rh, a.rl, w.ih, w.il, a.ih, a.il, w.rh, w.rl, 1.0f, r.ih, r.il);
+    return r;
+}
+__device__ __forceinline__ CF cf_mulc(const CF &a, const CF &w)  // a * conj(w)
+{
+    CF r;
+    ff_dot2(a.rh, a.rl, w.rh, w.rl, a.ih, a.il, w.ih, w.il, 1.0f, r.rh, r.rl);
+    ff_dot2(a.ih, a.il, w.rh, w.rl, a.rh, a.rl, w.ih, w.il, -1.0f, r.ih, r.il);
+    return r;
+}
+__device__ __forceinline__ CF cf_from(double re, double im)
+{
+    CF r;
+    r.rh = (float)re;
+    r.rl = (float)(re - (double)r.rh);
+    r.ih = (float)im;
+    r.il = (float)(im - (double)r.ih);
+    return r;
+}
+__device__ __forceinline__ double2 cf_to(const CF &a)
+{
+    return make_double2((double)a.rh + (double)a.rl, (double)a.ih + (double)a.il);
+}
+__device__ __forceinline__ CF ld_cf(const float4 *p)
+{
+    const float4 v = *p;
+    return CF{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void st_cf(float4 *p, const CF &a) { *p = make_float4(a.rh, a.rl, a.ih, a.il); }
+
+// The LDS passes of lds_pass in split precision (twf: split twiddles).
+template <int K, bool INV>
+__device__ __forceinline__ void lds_pass_ff(float4 *x, int lg, int nb, int s_lo, const float4 *twf)
+{
+    constexpr int G = 1 << K;
+    const int n = 1 << lg;
+    const int s_hi = s_lo + K - 1;
+    const int per = n >> K;
+    const int groups = nb * per;
+    const int jmask = (1 << s_lo) - 1;
+    for (int gi = threadIdx.x; gi < groups; gi += WG) {
+        const int b = gi / per;
+        const int r = gi - b * per;
+        const int j = r & jmask;
+        const int blk = r >> s_lo;
+        const int base = b * n + (blk << (s_hi + 1)) + j;
+        CF v[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) v[q] = ld_cf(x + base + (q << s_lo));
+        if (!INV) {
+#pragma unroll
+            for (int t = K - 1; t >= 0; --t) {
+                const int s = s_lo + t;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
+                    const CF w = ld_cf(twf + (jj << (10 - s)));
+                    const CF u = v[q], z = v[q + (1 << t)];
+                    v[q] = cf_add(u, z);
+                    v[q + (1 << t)] = cf_mul(cf_sub(u, z), w);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const int s = s_lo + t;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
+                    const CF w = ld_cf(twf + (jj << (10 - s)));
+                    const CF u = v[q], z = cf_mulc(v[q + (1 << t)], w);
+                    v[q] = cf_add(u, z);
+                    v[q + (1 << t)] = cf_sub(u, z);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) st_cf(x + base + (q << s_lo), v[q]);
+    }
+    __syncthreads();
+}
+
+__device__ void lds_dif_ff(float4 *x, int lg, int nb, const float4 *twf)
+{
+    int s_hi = lg - 1;
+    while (s_hi >= 0) {
+        const int k = s_hi + 1 >= 3 ? 3 : s_hi + 1;
+        const int s_lo = s_hi - k + 1;
+        if (k == 3) lds_pass_ff<3, false>(x, lg, nb, s_lo, twf);
+        else if (k == 2) lds_pass_ff<2, false>(x, lg, nb, s_lo, twf);
+        else lds_pass_ff<1, false>(x, lg, nb, s_lo, twf);
+        s_hi = s_lo - 1;
+    }
+}
+
+__device__ void lds_dit_inv_ff(float4 *x, int lg, int nb, const float4 *twf)
+{
+    int s_lo = 0;
+    while (s_lo < lg) {
+        const int k = lg - s_lo >= 3 ? 3 : lg - s_lo;
+        if (k == 3) lds_pass_ff<3, true>(x, lg, nb, s_lo, twf);
+        else if (k == 2) lds_pass_ff<2, true>(x, lg, nb, s_lo, twf);
+        else lds_pass_ff<1, true>(x, lg, nb, s_lo, twf);
+        s_lo += k;
+    }
+}
+
 // ------------------------------------------------- h-step kernel spectrum
 // Correlation y_m = sum_t W_t x_{m+t} with the h-fold one-step stencil has
 // DFT multiplier P(theta)^h, P(theta) = sum_t w_t e^{i t theta}.  Evaluated in
@@ -329,7 +503,7 @@ struct JobArgs {
     double2 *scr;
     ll n_in, h, out_off, n_out;
     double beta, tc;
-    int desc, lgN, kind, ntile, nph, pad;
+    int desc, lgN, kind, ntile, nph, prec;  // prec: 0 FP64, 1 split FP32
 };
 static_assert(sizeof(JobArgs) == 96, "job arguments are 96 bytes");
 
@@ -345,6 +519,7 @@ __device__ __forceinline__ JobArgs uni_args(JobArgs a)
     u.kind = __builtin_amdgcn_readfirstlane(a.kind);
     u.ntile = __builtin_amdgcn_readfirstlane(a.ntile);
     u.nph = __builtin_amdgcn_readfirstlane(a.nph);
+    u.prec = __builtin_amdgcn_readfirstlane(a.prec);
     return u;
 }
 
@@ -449,6 +624,128 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
     __syncthreads();
 }
 
+// The same tiles in split precision (JobArgs::prec == 1): rows enter as FP64,
+// are split to hi/lo FP32 and transformed with the split arithmetic above;
+// the kernel power (FP64) and the four-step twiddles (from the FP64 table) are
+// applied in FP64 to the recombined value, which is split again.  Scratch
+// holds one split complex (16 bytes) per point, like the FP64 path.
+__device__ __forceinline__ CF cf_scale64(const CF &a, double2 m)  // split(a * m), product in FP64
+{
+    const double2 x = cf_to(a);
+    return cf_from(x.x * m.x - x.y * m.y, x.x * m.y + x.y * m.x);
+}
+__device__ __forceinline__ CF cf_scale64c(const CF &a, double2 m)  // split(a * conj(m))
+{
+    const double2 x = cf_to(a);
+    return cf_from(x.x * m.x + x.y * m.y, x.y * m.x - x.x * m.y);
+}
+
+__device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float4 *lds, const double2 *__restrict__ tw,
+                                            const float4 *twf)
+{
+    const int lgN = j.lgN;
+    const ll N = ll(1) << lgN;
+    const double invN = 1.0 / (double)N;
+    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const int tid = threadIdx.x;
+    for (int t = tid; t < N; t += WG) st_cf(lds + t, cf_from(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0));
+    __syncthreads();
+    lds_dif_ff(lds, lgN, 1, twf);
+    for (ll f = tid; f <= N / 2; f += WG) {
+        const double2 m = kernel_power(q, f, lgN, tw);
+        const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
+        st_cf(lds + t1, cf_scale64(ld_cf(lds + t1), m));
+        if (t2 != t1) st_cf(lds + t2, cf_scale64c(ld_cf(lds + t2), m));
+    }
+    __syncthreads();
+    lds_dit_inv_ff(lds, lgN, 1, twf);
+    for (ll t = tid; t < j.n_out; t += WG) {
+        const CF v = ld_cf(lds + j.out_off + t);
+        j.dst[t] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, j.out_off + t);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_col_fwd_ff(const JobArgs &j, int tile, float4 *lds, const double2 *__restrict__ tw,
+                                                const float4 *twf)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int twsh = LG_TW - lgN;
+    const ll n20 = (ll)tile * C;
+    const int tid = threadIdx.x;
+    float4 *scr = (float4 *)j.scr;
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, n1 = t / C;
+        const ll idx = (ll)n1 * N2 + n20 + c;
+        st_cf(lds + c * N1 + n1, cf_from(idx < j.n_in ? tilt_in(j.src[idx], j.beta, idx, j.tc) : 0.0, 0.0));
+    }
+    __syncthreads();
+    lds_dif_ff(lds, lg1, C, twf);
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, p1 = t / C;
+        const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
+        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        st_cf(scr + (ll)p1 * N2 + n2, cf_scale64(ld_cf(lds + c * N1 + p1), w));
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_rows_ff(const Mp &p, const JobArgs &j, int tile, float4 *lds,
+                                             const double2 *__restrict__ tw, const float4 *twf)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1;
+    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const int tid = threadIdx.x;
+    const int p1 = tile;
+    const ll k1 = bitrev(p1, lg1);
+    float4 *row = (float4 *)j.scr + (ll)p1 * N2;
+    for (int t = tid; t < N2; t += WG) lds[t] = row[t];
+    __syncthreads();
+    lds_dif_ff(lds, lg2, 1, twf);
+    for (int t = tid; t < N2; t += WG) {
+        const ll k2 = bitrev(t, lg2);
+        st_cf(lds + t, cf_scale64(ld_cf(lds + t), kernel_power(q, k1 + (ll)N1 * k2, lgN, tw)));
+    }
+    __syncthreads();
+    lds_dit_inv_ff(lds, lg2, 1, twf);
+    for (int t = tid; t < N2; t += WG) row[t] = lds[t];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_col_inv_ff(const JobArgs &j, int tile, float4 *lds, const double2 *__restrict__ tw,
+                                                const float4 *twf)
+{
+    const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
+    const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
+    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int twsh = LG_TW - lgN;
+    const double invN = 1.0 / (double)N;
+    const ll n20 = (ll)tile * C;
+    const int tid = threadIdx.x;
+    const float4 *scr = (const float4 *)j.scr;
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, p1 = t / C;
+        const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
+        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        st_cf(lds + c * N1 + p1, cf_scale64c(ld_cf(scr + (ll)p1 * N2 + n2), w));
+    }
+    __syncthreads();
+    lds_dit_inv_ff(lds, lg1, C, twf);
+    for (int t = tid; t < NLDS; t += WG) {
+        const int c = t % C, n1 = t / C;
+        const ll idx = (ll)n1 * N2 + n20 + c;
+        if (idx >= j.out_off && idx < j.out_off + j.n_out) {
+            const CF v = ld_cf(lds + c * N1 + n1);
+            j.dst[idx - j.out_off] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, idx);
+        }
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------ direct correlation
 // For short steps the h-step correlation is evaluated as h applications of
 // the one-step linear stencil -- the backward recurrence itself without the
@@ -509,7 +806,7 @@ __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 
 // One tile of a job, executed by the whole workgroup (control flow uniform).
 __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, int t, double2 *lds,
-                                         const double2 *__restrict__ tw, const double2 *twl)
+                                         const double2 *__restrict__ tw, const double2 *twl, const float4 *twf)
 {
     if (j.kind == K_DIRECT) {
         if (threadIdx.x < 64) {
@@ -519,6 +816,12 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
             else direct_wave<16>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
         }
         __syncthreads();
+    } else if (j.prec) {
+        float4 *l4 = (float4 *)lds;
+        if (j.kind == K_LDS) tile_lds_ff(p, j, l4, tw, twf);
+        else if (ph == 0) tile_col_fwd_ff(j, t, l4, tw, twf);
+        else if (ph == 1) tile_rows_ff(p, j, t, l4, tw, twf);
+        else tile_col_inv_ff(j, t, l4, tw, twf);
     } else if (j.kind == K_LDS) {
         tile_lds(p, j, lds, tw, twl);
     } else if (ph == 0) {
@@ -905,7 +1208,8 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
                                         int tile)
 {
     if (a.desc < 0 || a.desc >= n || a.kind < K_DIRECT || a.kind > K_4STEP || a.lgN < 1 || a.lgN > LG_TW ||
-        ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN))
+        ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN) ||
+        a.prec < 0 || a.prec > 1)
         return false;
     const Desc d = descs[a.desc];
     if (d.model < 0) return false;
@@ -925,7 +1229,8 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
 // found nothing to claim for `idle_ticks` (helpers are never needed for
 // progress: drivers finish their own jobs).
 __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs, const char *ws, Shared *sh,
-                            double2 *lds, const double2 *__restrict__ tw, const double2 *twl, ll idle_ticks)
+                            double2 *lds, const double2 *__restrict__ tw, const double2 *twl, const float4 *twf,
+                            ll idle_ticks)
 {
     ll last_work = now_ticks();
     const int tid = threadIdx.x;
@@ -990,7 +1295,7 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
         const int ph = (msg >> 4) & 15, tile = msg >> 8;
         if (args_ok(descs, n, ws, a, ph, tile)) {
             const Mp p = make_mp(descs[a.desc]);
-            run_tile(p, a, ph, tile, lds, tw, twl);
+            run_tile(p, a, ph, tile, lds, tw, twl, twf);
         } else if (tid == 0) {
             set_abort(pl);
         }
@@ -1030,6 +1335,8 @@ struct Ctx {
     double2 *lds;
     const double2 *tw;
     const double2 *twl;
+    const float4 *twf;
+    int prec;  // 0 FP64, 1 split-FP32 FFT correlations
     ll *bnd;
     Pool pl;
     Tune tn;
@@ -1080,12 +1387,12 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     a.beta = beta;
     a.tc = tc;
     a.desc = cx.desc;
-    a.pad = 0;
     int lgN = ceil_log2(n_in);
     if (lgN < 1) lgN = 1;
     a.lgN = lgN;
     const bool direct = beta == 0.0 && h <= cx.tn.direct_max_h && n_in <= cx.tn.direct_max_n;
     a.kind = direct ? K_DIRECT : (lgN <= LG_NLDS ? K_LDS : K_4STEP);
+    a.prec = direct ? 0 : cx.prec;  // direct stepping is always FP64
     a.nph = a.kind == K_4STEP ? 3 : 1;
     a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
     const ll need = a.kind == K_4STEP ? (ll(1) << lgN) : 0;
@@ -1170,7 +1477,7 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
         }
         if ((msg & 15) == 2) {
             const ll tb = clk();
-            run_tile(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl);
+            run_tile(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf);
             if (mode == 1 && threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
             work += clk() - tb;
         }
@@ -1602,7 +1909,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
 __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, const double2 *__restrict__ tw,
                                              double *price, ll *bnd, ll bnd_stride, int32_t *err, Stats *stats,
                                              const Pool &pl, const Tune &tn, double2 *lds, const double2 *twl,
-                                             Frame *stk, int *sp_sh, int *err_sh, ll *ret_sh, ll *leaf_sh,
+                                             const float4 *twf, Frame *stk, int *sp_sh, int *err_sh, ll *ret_sh, ll *leaf_sh,
                                              ll *red_sh, double *val_sh, Stats *st_sh, Shared *sh)
 {
     const int tid = threadIdx.x;
@@ -1623,6 +1930,8 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     cx.lds = lds;
     cx.tw = tw;
     cx.twl = twl;
+    cx.twf = twf;
+    cx.prec = d.prec;
     cx.bnd = bnd ? bnd + d.out_index * bnd_stride : nullptr;
     cx.st = st_sh;
     cx.pl = pl;
@@ -1662,6 +1971,7 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
 {
     __shared__ double2 lds[NLDS];
     __shared__ double2 twl[NLDS / 2];
+    __shared__ float4 twf[NLDS / 2];
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
     __shared__ ll ret_sh, leaf_sh, red_sh[WG / 64];
@@ -1670,7 +1980,12 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
     __shared__ Shared sh;
 
     const int tid = threadIdx.x;
-    for (int t = tid; t < NLDS / 2; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS)];
+    for (int t = tid; t < NLDS / 2; t += WG) {
+        const double2 w = tw[(ll)t << (LG_TW - LG_NLDS)];
+        twl[t] = w;
+        const CF c = cf_from(w.x, w.y);
+        twf[t] = make_float4(c.rh, c.rl, c.ih, c.il);
+    }
     for (int t = tid; t < JPW; t += WG) {
         sh.pub[t] = 0;
         sh.gen[t] = 0;
@@ -1690,12 +2005,12 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
                 __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
             }
         } else {
-            drive_option(d, o, ws, tw, price, bnd, bnd_stride, err, stats, pl, tn, lds, twl, stk, &sp_sh, &err_sh,
+            drive_option(d, o, ws, tw, price, bnd, bnd_stride, err, stats, pl, tn, lds, twl, twf, stk, &sp_sh, &err_sh,
                          &ret_sh, &leaf_sh, red_sh, &val_sh, &st_sh, &sh);
         }
         __syncthreads();
     }
-    helper_loop(pl, n, descs, ws, &sh, lds, tw, twl, tn.idle_ticks);
+    helper_loop(pl, n, descs, ws, &sh, lds, tw, twl, twf, tn.idle_ticks);
 }
 
 // Clears the pool header, the summary bitmap and the slot words before a launch.
