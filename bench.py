@@ -72,6 +72,75 @@ def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
                       "thread, plain FP64 backward induction" % (len(sample), CONFIG_ID[model], sT)}
 
 
+def serve_bench(ctx, n_req: int, load: float = 0.7):
+    """Serving mix: closed-loop capacity, then an open loop of Poisson arrivals at load x capacity."""
+    import numpy as np
+
+    from paper_2303_02317_amd import binding, inputs
+
+    opts = inputs.serving_mix(n_req)
+    cells = np.array([float(o["T"]) ** 2 for o in opts])
+    cfg = dict(hbm_budget=48 << 30, max_inflight=4, max_batch=64)
+
+    def collect(srv, n, got, t_end=None):
+        while len(got) < n:
+            for r in srv.poll(8192, 2000):
+                got[r["id"]] = r
+            if t_end is not None and time.perf_counter() > t_end:
+                raise RuntimeError("serving run stalled: %s" % srv.stats())
+
+    # closed loop: everything queued at once
+    srv = binding.Server(ctx, **cfg)
+    t0 = time.perf_counter()
+    srv.submit(opts, list(range(len(opts))))
+    got = {}
+    collect(srv, len(opts), got, t0 + 600)
+    wall = time.perf_counter() - t0
+    st_closed = srv.stats()
+    srv.close()
+    cap = len(opts) / wall
+    log("serve closed loop: %d requests in %.2f s (%.0f options/s)" % (len(opts), wall, cap))
+    # open loop at `load` of the capacity
+    rate = load * cap
+    arr = inputs.poisson_arrivals(len(opts), rate)
+    srv = binding.Server(ctx, **cfg)
+    got2 = {}
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(opts):
+        now = time.perf_counter() - t0
+        j = k
+        while j < len(opts) and arr[j] <= now:
+            j += 1
+        if j > k:
+            srv.submit(opts[k:j], list(range(k, j)))
+            k = j
+        for r in srv.poll(8192, 0):
+            got2[r["id"]] = r
+        time.sleep(0.0002)
+    collect(srv, len(opts), got2, time.perf_counter() + 600)
+    wall2 = time.perf_counter() - t0
+    st_open = srv.stats()
+    srv.close()
+    lat = np.array([got2[i]["latency_s"] for i in range(len(opts))])
+    que = np.array([got2[i]["queue_s"] for i in range(len(opts))])
+    ok = all(got[i]["status"] == 0 for i in got) and all(got2[i]["status"] == 0 for i in got2)
+    same = all(got[i]["price"] == got2[i]["price"] for i in range(len(opts)))
+    log("serve open loop at %.0f/s: p50 %.1f ms p99 %.1f ms" % (rate, 1e3 * np.percentile(lat, 50),
+                                                              1e3 * np.percentile(lat, 99)))
+    return {"requests": len(opts), "mix": "model uniform {binomial call, trinomial call, BSM put}, "
+                                         "T = round(2^U[10,20]), parameters as the binomial batch, seed [5, 0]",
+            "closed_loop": {"seconds": wall, "options_per_s": cap, "cells_per_s": float(cells.sum()) / wall,
+                            "batches": st_closed["batches"], "peak_hbm_bytes": st_closed["peak_bytes"]},
+            "open_loop": {"arrival_rate_per_s": rate, "load": load, "seconds": wall2,
+                          "options_per_s": len(opts) / wall2, "cells_per_s": float(cells.sum()) / wall2,
+                          "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                          "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                          "queue_p50_ms": 1e3 * float(np.percentile(que, 50)),
+                          "batches": st_open["batches"], "peak_hbm_bytes": st_open["peak_bytes"]},
+            "config": dict(cfg, precision="fp64"), "all_ok": ok, "same_prices_both_runs": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +150,8 @@ def main():
     ap.add_argument("--options", type=int, default=64)
     ap.add_argument("--option-type", choices=sorted(TYPES), default="binomial")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="requests of the serving mix timed after the batch (0: skip)")
     ap.add_argument("--plain", action="store_true",
                     help="also time the plain Theta(T^2) GPU stencil on the same batch (one step)")
     args = ap.parse_args()
@@ -199,6 +270,9 @@ def main():
         agree = float(np.max(np.abs(pp - prices) / np.maximum(np.abs(pp), 1e-3 * np.array([o["K"] for o in opts]))))
         line["plain_gpu"] = {"value": cells / pw, "unit": "cells/s", "ms": pw * 1e3, "event_ms": e0.elapsed_time(e1),
                              "speedup_fft_vs_plain": pw / (wall / args.steps), "max_rel_diff_vs_fft": agree}
+    if args.serve_requests > 0:
+        log("serving mix ...")
+        line["serve"] = serve_bench(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(opts, model, args.log2T)

@@ -172,7 +172,7 @@ aop_status aop_pool_stats(const void *d_workspace, int64_t n, int64_t h_out[8]);
  * trapezoid are independent of its sub-trapezoids).
  */
 typedef struct {
-    int32_t workgroups;     /* persistent grid (0 = one per compute unit, at most 1024) */
+    int32_t workgroups;     /* persistent grid (0 = one per compute unit, at most 512) */
     int32_t pub_min_lg;     /* FFT correlations of size >= 2^pub_min_lg are published (1..30) */
     int32_t pub_direct;     /* 1: publish direct-stepping correlations too; 0: run them inline */
     int32_t direct_max_h;   /* correlations with h <= this (and n <= direct_max_n) step directly */
@@ -183,6 +183,58 @@ typedef struct {
 aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out);
 /* Returns AOP_EINVAL (and keeps the old tuning) for out-of-range fields. */
 aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *tuning);
+
+/*
+ * Serving: continuous batching of pricing requests of mixed model and T,
+ * priced by the persistent FFT-path kernel while new requests keep arriving.
+ *
+ * A server owns a device arena of hbm_budget bytes (its HBM budget) and a
+ * scheduler thread with max_inflight launch slots, each with its own HIP
+ * stream and 1/max_inflight of the compute units.  When a slot is free the
+ * scheduler takes the oldest pending request, adds younger requests of the same
+ * size class (model, ceil(log2 T)) in arrival order up to max_batch while the
+ * batch's workspace still fits in one free block of the arena (admission by
+ * HBM footprint), and launches it; batches admitted while others run overlap
+ * on the device.  Each option's schedule depends only on that option, so its
+ * price is bitwise the same alone and in any mix.
+ *
+ * The server uses the context's twiddle table and tuning: do not change the
+ * context's tuning, nor destroy it, while a server on it exists.  The server
+ * functions are thread-safe among themselves (submit and poll may run on
+ * different threads).
+ */
+typedef struct aop_server aop_server;
+
+typedef struct {
+    size_t hbm_budget;    /* device bytes for workspaces (0: a quarter of the free memory) */
+    int32_t max_inflight; /* batches on the device at once, 1..16 */
+    int32_t max_batch;    /* options per batch, 1..4096 */
+    int32_t precision;    /* AOP_FP64 or AOP_MIXED, for every request */
+    int32_t reserved;     /* must be 0 */
+} aop_server_config;
+
+typedef struct {
+    uint64_t id;         /* the caller's request id */
+    double price;        /* NaN unless status == AOP_OK */
+    int32_t status;      /* AOP_OK, the option's validation error, AOP_ENOMEM (larger than the whole
+                            budget), AOP_EDEVICE, or AOP_ECANCELED (server stopped on an error) */
+    int32_t batch_size;  /* options in the launch that priced it (0 if none) */
+    double queue_s;      /* seconds from submission to its launch */
+    double latency_s;    /* seconds from submission to the result being available on the host */
+} aop_result;
+
+aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_server **out);
+/* Queue n requests (host arrays, copied before return); arrival time is now. */
+aop_status aop_server_submit(aop_server *server, const aop_option *h_opts, const uint64_t *h_ids, int64_t n);
+/* Move up to max finished results to h_out (any order), waiting up to wait_us
+ * microseconds for the first one; *n_out = number written.  Returns the
+ * server's error state (AOP_OK while healthy). */
+aop_status aop_server_poll(aop_server *server, aop_result *h_out, int64_t max, int64_t *n_out, int32_t wait_us);
+/* h_out[0] submitted, [1] completed, [2] batches launched, [3] batches in flight,
+ * [4] requests pending, [5] peak arena bytes in use, [6] arena bytes, [7] workgroups per batch. */
+aop_status aop_server_stats(aop_server *server, int64_t h_out[8]);
+/* Finish every queued request, then release the server's device memory and streams. */
+aop_status aop_server_destroy(aop_server *server);
 
 /* Synchronous convenience: price one option, allocating and freeing its own
  * workspace.  h_boundary: NULL or a host array of T+1 int64. */

@@ -25,7 +25,8 @@ BSM_NONE = np.iinfo(np.int64).min
 #: Every symbol include/aop.h declares.
 EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
-           "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning"]
+           "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
+           "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
                 "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
@@ -41,6 +42,20 @@ class AopTuning(ctypes.Structure):
 
 class AopError(RuntimeError):
     pass
+
+
+class AopServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class AopResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("price", ctypes.c_double), ("status", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+SERVER_STATS = ["submitted", "completed", "batches", "inflight", "pending", "peak_bytes", "arena_bytes",
+                "workgroups_per_batch"]
 
 
 class AopOption(ctypes.Structure):
@@ -77,6 +92,11 @@ def load():
         "aop_pool_stats": (I32, [P, I64, P]),
         "aop_ctx_get_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
         "aop_ctx_set_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
+        "aop_server_create": (I32, [P, ctypes.POINTER(AopServerConfig), ctypes.POINTER(P)]),
+        "aop_server_submit": (I32, [P, P, P, I64]),
+        "aop_server_poll": (I32, [P, P, I64, ctypes.POINTER(I64), I32]),
+        "aop_server_stats": (I32, [P, P]),
+        "aop_server_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -254,3 +274,47 @@ def price_one(ctx: Context, opt, precision: int = AOP_FP64, boundary: bool = Fal
                        b.ctypes.data_as(ctypes.c_void_p) if b is not None else None)
     _check(rc, "aop_price")
     return (out.value, b) if boundary else out.value
+
+
+class Server:
+    """Continuous-batching server (aop_server_*): submit requests, poll results."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 0, max_inflight: int = 4, max_batch: int = 64,
+                 precision: int = AOP_FP64):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        cfg = AopServerConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(precision), 0)
+        _check(lib.aop_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self._h)), "aop_server_create")
+        self.ctx = ctx
+
+    def submit(self, opts, ids):
+        arr = options_array(opts)
+        idv = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+        _check(load().aop_server_submit(self._h, arr, idv.ctypes.data_as(ctypes.c_void_p), len(opts)),
+               "aop_server_submit")
+
+    def poll(self, max_results: int = 4096, wait_us: int = 1000):
+        """Finished results as a list of dicts (any order)."""
+        buf = (AopResult * max(1, max_results))()
+        n = ctypes.c_int64()
+        rc = load().aop_server_poll(self._h, buf, max_results, ctypes.byref(n), int(wait_us))
+        out = [dict(id=int(buf[i].id), price=buf[i].price, status=buf[i].status, batch_size=buf[i].batch_size,
+                    queue_s=buf[i].queue_s, latency_s=buf[i].latency_s) for i in range(n.value)]
+        _check(rc, "aop_server_poll")
+        return out
+
+    def stats(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(load().aop_server_stats(self._h, out.ctypes.data_as(ctypes.c_void_p)), "aop_server_stats")
+        return {f: int(out[i]) for i, f in enumerate(SERVER_STATS)}
+
+    def close(self):
+        if self._h:
+            load().aop_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,27 +14,14 @@
 #include <vector>
 
 #include "aop.h"
+#include "aop_host.h"
 #include "aop_internal.h"
 
 using aop::Desc;
 
-struct aop_ctx {
-    int device = 0;
-    double lambda = 1.0 / 3.0;
-    void *d_tw = nullptr;          // twiddle table, TW_N complex doubles
-    Desc *h_stage = nullptr;       // pinned staging for descriptors
-    size_t stage_cap = 0;          // descriptors
-    hipEvent_t stage_done = nullptr;
-    bool stage_pending = false;
-    int n_cu = 0;                  // compute units of the device
-    double tick_hz = 1e8;          // device wall clock (s_memrealtime) frequency
-    aop_tuning tuning{};           // launch tuning of the solve kernel
-};
-
 namespace {
 
-constexpr size_t ALIGN = 256;
-inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+inline size_t align_up(size_t x) { return aop::ws_align(x); }
 inline int64_t next_pow2(int64_t n)
 {
     int64_t p = 1;
@@ -150,9 +137,29 @@ size_t option_bytes(const Desc &d)
     return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.scr_len);
 }
 
+// Descriptors for the plain stencil: two row buffers per option.
+size_t build_plain(const aop_option *opts, int64_t n, double lambda, Desc *out, int32_t *status)
+{
+    size_t off = align_up(sizeof(Desc) * (size_t)std::max<int64_t>(n, 1));
+    for (int64_t i = 0; i < n; ++i) {
+        Desc &d = out[i];
+        aop_status st = make_desc(opts[i], lambda, d);
+        d.out_index = i;
+        if (status) status[i] = st;
+        if (st != AOP_OK) {
+            d.model = -1;
+            continue;
+        }
+        geometry(d);
+        d.ws_off = (int64_t)off;
+        off += align_up(sizeof(double) * 2 * (size_t)d.row_len);
+    }
+    return off;
+}
+
 // Estimated solve cost of an option (work ~ T log^2 T; the trinomial and BSM
 // rows are twice as long), used to hand out the largest options first.
-double option_cost(const Desc &d)
+static double option_cost(const Desc &d)
 {
     if (d.model < 0) return -1.0;
     const double T = (double)d.T, lg = std::log2(T + 1.0);
@@ -163,6 +170,10 @@ double option_cost(const Desc &d)
 // are stored in decreasing order of estimated cost (the order in which the
 // persistent kernel's workgroups claim them); out_index keeps each option's
 // position in the caller's arrays.
+}  // namespace
+
+namespace aop {
+
 size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambda, Desc *out, int32_t *status)
 {
     std::vector<Desc> tmp((size_t)std::max<int64_t>(n, 1));
@@ -196,25 +207,31 @@ size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambd
     return off;
 }
 
-// Descriptors for the plain stencil: two row buffers per option.
-size_t build_plain(const aop_option *opts, int64_t n, double lambda, Desc *out, int32_t *status)
+size_t option_area_bytes(const aop_option &o, double lambda)
 {
-    size_t off = align_up(sizeof(Desc) * (size_t)std::max<int64_t>(n, 1));
-    for (int64_t i = 0; i < n; ++i) {
-        Desc &d = out[i];
-        aop_status st = make_desc(opts[i], lambda, d);
-        d.out_index = i;
-        if (status) status[i] = st;
-        if (st != AOP_OK) {
-            d.model = -1;
-            continue;
-        }
-        geometry(d);
-        d.ws_off = (int64_t)off;
-        off += align_up(sizeof(double) * 2 * (size_t)d.row_len);
-    }
-    return off;
+    Desc d;
+    if (make_desc(o, lambda, d) != AOP_OK) return 0;
+    geometry(d);
+    return option_bytes(d);
 }
+
+Tune make_tune(const aop_ctx &ctx, int32_t workgroups)
+{
+    Tune tune;
+    tune.workgroups = workgroups > 0 ? std::min(workgroups, MAX_WG) : ctx.tuning.workgroups;
+    tune.pub_min_lg = ctx.tuning.pub_min_lg;
+    tune.pub_direct = ctx.tuning.pub_direct;
+    tune.direct_max_h = ctx.tuning.direct_max_h;
+    tune.direct_max_n = ctx.tuning.direct_max_n;
+    tune.reserved = 0;
+    tune.timeout_ticks = (int64_t)(1e-3 * (double)ctx.tuning.timeout_ms * ctx.tick_hz);
+    tune.idle_ticks = (int64_t)(1e-6 * (double)ctx.tuning.helper_idle_us * ctx.tick_hz);
+    return tune;
+}
+
+}  // namespace aop
+
+namespace {
 
 aop_status ensure_stage(aop_ctx *ctx, size_t n)
 {
@@ -320,7 +337,7 @@ aop_status aop_workspace_bytes(const aop_option *opts, int64_t n, int32_t precis
 {
     if (!bytes || n < 0 || (n > 0 && !opts)) return AOP_EINVAL;
     std::vector<Desc> d((size_t)std::max<int64_t>(n, 1));
-    *bytes = build_batch(opts, n, precision, 1.0 / 3.0, d.data(), nullptr);
+    *bytes = aop::build_batch(opts, n, precision, 1.0 / 3.0, d.data(), nullptr);
     return AOP_OK;
 }
 
@@ -334,7 +351,7 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
     aop_status st = ensure_stage(ctx, (size_t)n);
     if (st != AOP_OK) return st;
     std::vector<int32_t> stat((size_t)n);
-    const size_t need = build_batch(opts, n, precision, ctx->lambda, ctx->h_stage, stat.data());
+    const size_t need = aop::build_batch(opts, n, precision, ctx->lambda, ctx->h_stage, stat.data());
     if (h_status) std::memcpy(h_status, stat.data(), sizeof(int32_t) * (size_t)n);
     if (ws_bytes < need) return AOP_ENOMEM;
     if (d_bnd) {
@@ -347,15 +364,7 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
         return AOP_EDEVICE;
     if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
     ctx->stage_pending = true;
-    aop::Tune tune;
-    tune.workgroups = ctx->tuning.workgroups;
-    tune.pub_min_lg = ctx->tuning.pub_min_lg;
-    tune.pub_direct = ctx->tuning.pub_direct;
-    tune.direct_max_h = ctx->tuning.direct_max_h;
-    tune.direct_max_n = ctx->tuning.direct_max_n;
-    tune.reserved = 0;
-    tune.timeout_ticks = (int64_t)(1e-3 * (double)ctx->tuning.timeout_ms * ctx->tick_hz);
-    tune.idle_ticks = (int64_t)(1e-6 * (double)ctx->tuning.helper_idle_us * ctx->tick_hz);
+    const aop::Tune tune = aop::make_tune(*ctx, 0);
     if (aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr, tune,
                           stream) != 0)
         return AOP_EDEVICE;

@@ -50,7 +50,7 @@ inline int64_t stats_offset(int64_t n) { return ((int64_t)sizeof(Desc) * (n > 0 
 // claimable tiles), one 64-bit word per workgroup whose bits flag those slots,
 // and JPW job slots per workgroup (128 B each).
 constexpr int JPW = 64;          // job slots per workgroup
-constexpr int MAX_WG = 1024;     // largest persistent grid
+constexpr int MAX_WG = 512;      // largest persistent grid
 struct PoolHdr {
     uint32_t next_option, n_wg;
     uint64_t status;  // options finished (low 32 bits) | launch aborted (bit 32)
@@ -59,7 +59,7 @@ struct PoolHdr {
 };
 static_assert(sizeof(PoolHdr) == 128, "pool header is 128 bytes");
 constexpr int64_t JOB_BYTES = 128;
-constexpr int64_t POOL_SUMMARY = 128;                 // byte offset of the summary bitmap (MAX_WG bits)
+constexpr int64_t POOL_SUMMARY = 128;                 // byte offset of the summary bitmap (up to 1024 bits)
 constexpr int64_t POOL_BITS = 256;                    // byte offset of the per-workgroup slot words
 constexpr int64_t POOL_JOBS = POOL_BITS + 8 * MAX_WG; // byte offset of the job slots
 constexpr int64_t POOL_BYTES = POOL_JOBS + JOB_BYTES * JPW * MAX_WG;
