@@ -124,6 +124,24 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *h_opts, int64_t n, in
                            void *hip_stream);
 
 /*
+ * Graph form of aop_price_batch: the batch's launch (clearing of the work
+ * pool and the persistent solve kernel) is captured once in a hipGraph and
+ * replayed with aop_graph_launch, for callers that price the same batch of
+ * options repeatedly.  Arguments as in aop_price_batch (the graph uses the
+ * context's tuning at creation time); the descriptors are written to
+ * d_workspace synchronously during creation.  d_workspace, d_price and
+ * d_boundary must stay allocated while the graph exists; each replay
+ * overwrites d_price (and d_boundary) with the same prices.  Replays on one
+ * workspace must not overlap.
+ */
+typedef struct aop_graph aop_graph;
+aop_status aop_graph_create(aop_ctx *ctx, const aop_option *h_opts, int64_t n, int32_t precision,
+                            void *d_workspace, size_t ws_bytes, double *d_price, int32_t *h_status,
+                            int64_t *d_boundary, int64_t boundary_stride, aop_graph **out);
+aop_status aop_graph_launch(aop_graph *graph, void *hip_stream);
+aop_status aop_graph_destroy(aop_graph *graph);
+
+/*
  * Comparison path: the plain Theta(T^2) backward induction of Fig. 1 on the
  * GPU (same arguments and semantics as aop_price_batch, FP64 only; the
  * boundary is not reported: pass NULL).  Workspace: aop_plain_workspace_bytes.
@@ -205,12 +223,26 @@ aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *tuning);
  */
 typedef struct aop_server aop_server;
 
+/* Tuning of one size class (the autotuner's output); workgroups is ignored by
+ * the server, which gives each batch 1/max_inflight of the compute units. */
+typedef struct {
+    int32_t model;      /* aop_model */
+    int32_t log2T;      /* ceil(log2 T) of the class */
+    int32_t precision;  /* aop_precision */
+    int32_t reserved;   /* must be 0 */
+    aop_tuning tuning;
+} aop_class_tuning;
+
 typedef struct {
     size_t hbm_budget;    /* device bytes for workspaces (0: a quarter of the free memory) */
     int32_t max_inflight; /* batches on the device at once, 1..16 */
     int32_t max_batch;    /* options per batch, 1..4096 */
     int32_t precision;    /* AOP_FP64 or AOP_MIXED, for every request */
     int32_t reserved;     /* must be 0 */
+    const aop_class_tuning *tunings; /* NULL, or n_tunings per-class schedules (copied at creation):
+                                        a batch uses the entry of its model and precision nearest
+                                        in log2T, else the context's tuning */
+    int64_t n_tunings;
 } aop_server_config;
 
 typedef struct {

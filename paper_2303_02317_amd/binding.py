@@ -26,7 +26,8 @@ BSM_NONE = np.iinfo(np.int64).min
 EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
            "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
-           "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy"]
+           "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
+           "aop_graph_create", "aop_graph_launch", "aop_graph_destroy"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
                 "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
@@ -44,9 +45,15 @@ class AopError(RuntimeError):
     pass
 
 
+class AopClassTuning(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("log2T", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tuning", AopTuning)]
+
+
 class AopServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tunings", ctypes.POINTER(AopClassTuning)), ("n_tunings", ctypes.c_int64)]
 
 
 class AopResult(ctypes.Structure):
@@ -97,6 +104,9 @@ def load():
         "aop_server_poll": (I32, [P, P, I64, ctypes.POINTER(I64), I32]),
         "aop_server_stats": (I32, [P, P]),
         "aop_server_destroy": (I32, [P]),
+        "aop_graph_create": (I32, [P, P, I64, I32, P, SZ, P, P, P, I64, ctypes.POINTER(P)]),
+        "aop_graph_launch": (I32, [P, P]),
+        "aop_graph_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -130,6 +140,11 @@ class Context:
     """An aop_ctx on one device (owns the twiddle table and a pinned staging buffer)."""
 
     def __init__(self, device: int = 0, lam: float = 1.0 / 3.0):
+        # PyTorch owns device memory and streams: bring its HIP state up
+        # before the library touches the runtime.
+        import torch
+
+        torch.cuda.init()
         lib = load()
         self._h = ctypes.c_void_p()
         _check(lib.aop_ctx_create(int(device), float(lam), ctypes.byref(self._h)), "aop_ctx_create")
@@ -280,10 +295,18 @@ class Server:
     """Continuous-batching server (aop_server_*): submit requests, poll results."""
 
     def __init__(self, ctx: Context, hbm_budget: int = 0, max_inflight: int = 4, max_batch: int = 64,
-                 precision: int = AOP_FP64):
+                 precision: int = AOP_FP64, tunings=None):
+        """tunings: [(model, log2T, precision, schedule dict)] per size class (the autotuner's table)."""
         lib = load()
         self._h = ctypes.c_void_p()
-        cfg = AopServerConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(precision), 0)
+        tab = list(tunings or [])
+        base = ctx.tuning()
+        arr = (AopClassTuning * max(1, len(tab)))()
+        for i, (m, lg, p, sched) in enumerate(tab):
+            arr[i] = AopClassTuning(int(m), int(lg), int(p), 0, AopTuning(**dict(base, **sched)))
+        self._tab = arr
+        cfg = AopServerConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(precision), 0,
+                              ctypes.cast(arr, ctypes.POINTER(AopClassTuning)) if tab else None, len(tab))
         _check(lib.aop_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self._h)), "aop_server_create")
         self.ctx = ctx
 
@@ -311,6 +334,46 @@ class Server:
     def close(self):
         if self._h:
             load().aop_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraph:
+    """A batch launch captured once in a hipGraph (aop_graph_*), replayed with launch()."""
+
+    def __init__(self, ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = False):
+        import torch
+
+        lib = load()
+        n = len(opts)
+        dev = torch.device("cuda", ctx.device)
+        arr = options_array(opts)
+        self.workspace = torch.empty(workspace_bytes(opts, precision), dtype=torch.uint8, device=dev)
+        self.price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        stride = max(int(o["T"]) for o in opts) + 1 if boundary else 0
+        self.boundary = torch.empty((n, stride), dtype=torch.int64, device=dev) if boundary else None
+        self.status = np.zeros(max(n, 1), dtype=np.int32)
+        self.n = n
+        self._h = ctypes.c_void_p()
+        torch.cuda.synchronize(dev)
+        _check(lib.aop_graph_create(ctx.handle, arr, n, int(precision), ctypes.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace.numel(), ctypes.c_void_p(self.price.data_ptr()),
+                                    self.status.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.c_void_p(self.boundary.data_ptr()) if boundary else None, stride,
+                                    ctypes.byref(self._h)), "aop_graph_create")
+
+    def launch(self, stream=None):
+        _check(load().aop_graph_launch(self._h, _stream_handle(stream)), "aop_graph_launch")
+        return self.price[:self.n]
+
+    def close(self):
+        if self._h:
+            load().aop_graph_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -215,18 +215,25 @@ size_t option_area_bytes(const aop_option &o, double lambda)
     return option_bytes(d);
 }
 
-Tune make_tune(const aop_ctx &ctx, int32_t workgroups)
+Tune make_tune(const aop_tuning &t, double tick_hz, int32_t workgroups)
 {
     Tune tune;
-    tune.workgroups = workgroups > 0 ? std::min(workgroups, MAX_WG) : ctx.tuning.workgroups;
-    tune.pub_min_lg = ctx.tuning.pub_min_lg;
-    tune.pub_direct = ctx.tuning.pub_direct;
-    tune.direct_max_h = ctx.tuning.direct_max_h;
-    tune.direct_max_n = ctx.tuning.direct_max_n;
+    tune.workgroups = workgroups > 0 ? std::min(workgroups, MAX_WG) : t.workgroups;
+    tune.pub_min_lg = t.pub_min_lg;
+    tune.pub_direct = t.pub_direct;
+    tune.direct_max_h = t.direct_max_h;
+    tune.direct_max_n = t.direct_max_n;
     tune.reserved = 0;
-    tune.timeout_ticks = (int64_t)(1e-3 * (double)ctx.tuning.timeout_ms * ctx.tick_hz);
-    tune.idle_ticks = (int64_t)(1e-6 * (double)ctx.tuning.helper_idle_us * ctx.tick_hz);
+    tune.timeout_ticks = (int64_t)(1e-3 * (double)t.timeout_ms * tick_hz);
+    tune.idle_ticks = (int64_t)(1e-6 * (double)t.helper_idle_us * tick_hz);
     return tune;
+}
+
+bool tuning_valid(const aop_tuning &u)
+{
+    return u.workgroups >= 1 && u.workgroups <= MAX_WG && u.pub_min_lg >= 1 && u.pub_min_lg <= 30 &&
+           u.direct_max_h >= 0 && u.direct_max_n >= 0 && u.direct_max_n <= 1024 && u.helper_idle_us >= 1 &&
+           u.timeout_ms > 0 && u.timeout_ms <= 3600000;
 }
 
 }  // namespace aop
@@ -379,6 +386,73 @@ aop_status aop_plain_workspace_bytes(const aop_option *opts, int64_t n, size_t *
     return AOP_OK;
 }
 
+struct aop_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+aop_status aop_graph_create(aop_ctx *ctx, const aop_option *opts, int64_t n, int32_t precision, void *d_ws,
+                            size_t ws_bytes, double *d_price, int32_t *h_status, int64_t *d_bnd,
+                            int64_t bnd_stride, aop_graph **out)
+{
+    if (!ctx || !out || n <= 0 || !opts || !d_ws || !d_price) return AOP_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    std::vector<Desc> descs((size_t)n);
+    std::vector<int32_t> stat((size_t)n);
+    const size_t need = aop::build_batch(opts, n, precision, ctx->lambda, descs.data(), stat.data());
+    if (h_status) std::memcpy(h_status, stat.data(), sizeof(int32_t) * (size_t)n);
+    if (ws_bytes < need) return AOP_ENOMEM;
+    if (d_bnd) {
+        int64_t tmax = 0;
+        for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, opts[i].T);
+        if (bnd_stride < tmax + 1) return AOP_EINVAL;
+    }
+    // the descriptors are written once, outside the graph: a replay reads nothing from the host
+    if (hipMemcpy(d_ws, descs.data(), sizeof(Desc) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess)
+        return AOP_EDEVICE;
+    aop_graph *g = new (std::nothrow) aop_graph;
+    if (!g) return AOP_ENOMEM;
+    g->device = ctx->device;
+    hipStream_t cs = nullptr;
+    aop_status rc = AOP_OK;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = AOP_EDEVICE;
+    if (rc == AOP_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = AOP_EDEVICE;
+    if (rc == AOP_OK) {
+        const aop::Tune tune = aop::make_tune(*ctx, 0);
+        const int lr = aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride,
+                                         nullptr, tune, cs);
+        const hipError_t e = hipStreamEndCapture(cs, &g->graph);
+        if (lr != 0 || e != hipSuccess) rc = AOP_EDEVICE;
+    }
+    if (rc == AOP_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) rc = AOP_EDEVICE;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != AOP_OK) {
+        aop_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return AOP_OK;
+}
+
+aop_status aop_graph_launch(aop_graph *g, void *stream)
+{
+    if (!g || !g->exec) return AOP_EINVAL;
+    if (hipSetDevice(g->device) != hipSuccess) return AOP_EDEVICE;
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? AOP_OK : AOP_EDEVICE;
+}
+
+aop_status aop_graph_destroy(aop_graph *g)
+{
+    if (!g) return AOP_EINVAL;
+    (void)hipSetDevice(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return AOP_OK;
+}
+
 aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *opts, int64_t n, void *d_ws,
                                  size_t ws_bytes, double *d_price, int32_t *h_status, void *stream)
 {
@@ -480,10 +554,7 @@ aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *t)
     if (!ctx || !t) return AOP_EINVAL;
     aop_tuning u = *t;
     if (u.workgroups == 0) u.workgroups = std::min(ctx->n_cu, aop::MAX_WG);
-    if (u.workgroups < 1 || u.workgroups > aop::MAX_WG || u.pub_min_lg < 1 || u.pub_min_lg > 30 ||
-        u.direct_max_h < 0 || u.direct_max_n < 0 || u.direct_max_n > 1024 || u.helper_idle_us < 1 ||
-        u.timeout_ms <= 0 || u.timeout_ms > 3600000)
-        return AOP_EINVAL;
+    if (!aop::tuning_valid(u)) return AOP_EINVAL;
     ctx->tuning = u;
     return AOP_OK;
 }

@@ -37,8 +37,10 @@ size_t build_batch(const aop_option *opts, int64_t n, int32_t prec, double lambd
 size_t option_area_bytes(const aop_option &o, double lambda);
 inline size_t batch_fixed_bytes(int64_t n) { return (size_t)options_offset(n); }
 
-// Kernel tuning from the context's settings, on `workgroups` workgroups (0:
-// the context's own setting).
-Tune make_tune(const aop_ctx &ctx, int32_t workgroups);
+// Kernel tuning from public settings (device clock rate tick_hz), on
+// `workgroups` workgroups (0: the settings' own).
+Tune make_tune(const aop_tuning &t, double tick_hz, int32_t workgroups);
+bool tuning_valid(const aop_tuning &t);
+inline Tune make_tune(const aop_ctx &ctx, int32_t workgroups) { return make_tune(ctx.tuning, ctx.tick_hz, workgroups); }
 
 }  // namespace aop

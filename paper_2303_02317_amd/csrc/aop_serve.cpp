@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -137,6 +138,7 @@ struct aop_server {
     Arena arena;
     std::vector<Slot> slots;
     int wg_per_batch = 1;
+    std::vector<aop_class_tuning> tunings;  // per size class (may be empty)
 
     std::mutex mu;
     std::condition_variable cv;
@@ -163,7 +165,18 @@ bool aop_server::launch(Slot &sl, std::vector<Request> &&batch, size_t bytes)
     if (need > bytes) return false;
     char *ws = d_arena + sl.off;
     double *d_price = (double *)(ws + need);  // prices after the batch's own workspace
-    const aop::Tune tune = aop::make_tune(*ctx, wg_per_batch);
+    // the schedule of the batch's class: the tuned entry nearest in log2 T
+    const aop_tuning *tsel = &ctx->tuning;
+    int best = 1 << 30;
+    for (const auto &e : tunings) {
+        if (e.model != sl.opts[0].model || e.precision != cfg.precision) continue;
+        const int d = std::abs(e.log2T - (sl.reqs[0].klass & 63));
+        if (d < best) {
+            best = d;
+            tsel = &e.tuning;
+        }
+    }
+    const aop::Tune tune = aop::make_tune(*tsel, ctx->tick_hz, wg_per_batch);
     if (hipMemcpyAsync(ws, sl.h_desc, sizeof(aop::Desc) * (size_t)n, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
         return false;
     if (aop::launch_solve((const aop::Desc *)ws, n, ws, ctx->d_tw, d_price, nullptr, 0, nullptr, tune, sl.stream) != 0)
@@ -339,10 +352,18 @@ aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_ser
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) return AOP_EDEVICE;
         c.hbm_budget = fr / 4;
     }
+    if (c.n_tunings < 0 || (c.n_tunings > 0 && !c.tunings)) return AOP_EINVAL;
+    for (int64_t i = 0; i < c.n_tunings; ++i) {
+        aop_tuning t = c.tunings[i].tuning;
+        t.workgroups = 1;  // replaced per batch
+        if (!aop::tuning_valid(t) || c.tunings[i].reserved != 0) return AOP_EINVAL;
+    }
     aop_server *s = new (std::nothrow) aop_server;
     if (!s) return AOP_ENOMEM;
     s->ctx = ctx;
     s->cfg = c;
+    s->tunings.assign(c.tunings, c.tunings + c.n_tunings);
+    s->cfg.tunings = nullptr;
     s->arena_bytes = aop::ws_align(c.hbm_budget);
     if (hipMalloc((void **)&s->d_arena, s->arena_bytes) != hipSuccess) {
         delete s;
