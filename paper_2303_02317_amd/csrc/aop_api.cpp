@@ -223,7 +223,7 @@ Tune make_tune(const aop_tuning &t, double tick_hz, int32_t workgroups)
     tune.pub_direct = t.pub_direct;
     tune.direct_max_h = t.direct_max_h;
     tune.direct_max_n = t.direct_max_n;
-    tune.reserved = 0;
+    tune.prec = 0;
     tune.timeout_ticks = (int64_t)(1e-3 * (double)t.timeout_ms * tick_hz);
     tune.idle_ticks = (int64_t)(1e-6 * (double)t.helper_idle_us * tick_hz);
     return tune;
@@ -371,7 +371,8 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
         return AOP_EDEVICE;
     if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
     ctx->stage_pending = true;
-    const aop::Tune tune = aop::make_tune(*ctx, 0);
+    aop::Tune tune = aop::make_tune(*ctx, 0);
+    tune.prec = precision;
     if (aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr, tune,
                           stream) != 0)
         return AOP_EDEVICE;
@@ -420,7 +421,8 @@ aop_status aop_graph_create(aop_ctx *ctx, const aop_option *opts, int64_t n, int
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = AOP_EDEVICE;
     if (rc == AOP_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = AOP_EDEVICE;
     if (rc == AOP_OK) {
-        const aop::Tune tune = aop::make_tune(*ctx, 0);
+        aop::Tune tune = aop::make_tune(*ctx, 0);
+        tune.prec = precision;
         const int lr = aop::launch_solve((const Desc *)d_ws, n, (char *)d_ws, ctx->d_tw, d_price, d_bnd, bnd_stride,
                                          nullptr, tune, cs);
         const hipError_t e = hipStreamEndCapture(cs, &g->graph);

@@ -176,7 +176,8 @@ bool aop_server::launch(Slot &sl, std::vector<Request> &&batch, size_t bytes)
             tsel = &e.tuning;
         }
     }
-    const aop::Tune tune = aop::make_tune(*tsel, ctx->tick_hz, wg_per_batch);
+    aop::Tune tune = aop::make_tune(*tsel, ctx->tick_hz, wg_per_batch);
+    tune.prec = cfg.precision;
     if (hipMemcpyAsync(ws, sl.h_desc, sizeof(aop::Desc) * (size_t)n, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
         return false;
     if (aop::launch_solve((const aop::Desc *)ws, n, ws, ctx->d_tw, d_price, nullptr, 0, nullptr, tune, sl.stream) != 0)

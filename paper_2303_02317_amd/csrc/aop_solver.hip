@@ -805,6 +805,7 @@ __device__ __forceinline__ void direct_wave(Mp p, const double *__restrict__ src
 __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 
 // One tile of a job, executed by the whole workgroup (control flow uniform).
+template <int PREC>
 __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, int t, double2 *lds,
                                          const double2 *__restrict__ tw, const double2 *twl, const float4 *twf)
 {
@@ -816,7 +817,7 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
             else direct_wave<16>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
         }
         __syncthreads();
-    } else if (j.prec) {
+    } else if (PREC) {
         float4 *l4 = (float4 *)lds;
         if (j.kind == K_LDS) tile_lds_ff(p, j, l4, tw, twf);
         else if (ph == 0) tile_col_fwd_ff(j, t, l4, tw, twf);
@@ -1205,11 +1206,11 @@ struct Shared {
 // A claimed job's arguments must describe ranges inside its option's own
 // workspace area (rows, arena, FFT scratch); anything else is refused.
 __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, const char *ws, const JobArgs &a, int ph,
-                                        int tile)
+                                        int tile, int prec)
 {
     if (a.desc < 0 || a.desc >= n || a.kind < K_DIRECT || a.kind > K_4STEP || a.lgN < 1 || a.lgN > LG_TW ||
         ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN) ||
-        a.prec < 0 || a.prec > 1)
+        a.prec < 0 || a.prec > 1 || (a.kind != K_DIRECT && a.prec != prec))
         return false;
     const Desc d = descs[a.desc];
     if (d.model < 0) return false;
@@ -1228,6 +1229,7 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
 // A helper leaves once every option is done, the launch aborted, or it has
 // found nothing to claim for `idle_ticks` (helpers are never needed for
 // progress: drivers finish their own jobs).
+template <int PREC>
 __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs, const char *ws, Shared *sh,
                             double2 *lds, const double2 *__restrict__ tw, const double2 *twl, const float4 *twf,
                             ll idle_ticks)
@@ -1293,9 +1295,9 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
         if ((msg & 15) != 1) continue;
         const ll t0 = clk();
         const int ph = (msg >> 4) & 15, tile = msg >> 8;
-        if (args_ok(descs, n, ws, a, ph, tile)) {
+        if (args_ok(descs, n, ws, a, ph, tile, PREC)) {
             const Mp p = make_mp(descs[a.desc]);
-            run_tile(p, a, ph, tile, lds, tw, twl, twf);
+            run_tile<PREC>(p, a, ph, tile, lds, tw, twl, twf);
         } else if (tid == 0) {
             set_abort(pl);
         }
@@ -1372,6 +1374,7 @@ __device__ __forceinline__ void set_err(const Ctx &cx, int e)
 // jobs are published to the pool; the others stay private to the driver.
 // Either way the work is done (or finished) by conv_wait.  Returns the scratch
 // (complex elements) the job holds until then.
+template <int PREC>
 __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, const double *src, ll n_in, ll h,
                                           ll out_off, ll n_out, double *dst, double beta = 0.0, double tc = 0.0)
 {
@@ -1392,7 +1395,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     a.lgN = lgN;
     const bool direct = beta == 0.0 && h <= cx.tn.direct_max_h && n_in <= cx.tn.direct_max_n;
     a.kind = direct ? K_DIRECT : (lgN <= LG_NLDS ? K_LDS : K_4STEP);
-    a.prec = direct ? 0 : cx.prec;  // direct stepping is always FP64
+    a.prec = direct ? 0 : PREC;  // direct stepping is always FP64
     a.nph = a.kind == K_4STEP ? 3 : 1;
     a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
     const ll need = a.kind == K_4STEP ? (ll(1) << lgN) : 0;
@@ -1427,6 +1430,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
 // Finish the pending job of `slot`: a private job's tiles are computed here
 // in order; for a published one the driver takes the tiles no other
 // workgroup has claimed and waits for the rest.
+template <int PREC>
 __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
 {
     const int mode = __builtin_amdgcn_readfirstlane(cx.sh->pub[slot]);
@@ -1477,7 +1481,7 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
         }
         if ((msg & 15) == 2) {
             const ll tb = clk();
-            run_tile(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf);
+            run_tile<PREC>(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf);
             if (mode == 1 && threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
             work += clk() - tb;
         }
@@ -1537,6 +1541,7 @@ __device__ __forceinline__ double read_result(const double *p)
 // while the second is, and the frame ends only after both are done.  Each
 // iteration first finishes the frame's pending correlation (stages 1 and 2),
 // then takes the frame one stage further, which may submit one correlation.
+template <int PREC>
 __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh, ll *ret_sh,
                                               ll *leaf_sh)
 {
@@ -1562,7 +1567,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
         const int slot = s + 1;
         const ll rv = uni(*ret_sh);
         __syncthreads();
-        if (fr.stage > 0) conv_wait(cx, slot);
+        if (fr.stage > 0) conv_wait<PREC>(cx, slot);
         bool pop = false, leaf = false;
         ll result = 0;
         Frame child;
@@ -1689,7 +1694,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             result = *leaf_sh;
         }
         if (e == DEV_OK && !pop && cout > 0)
-            child.soff = fr.soff + conv_submit(cx, slot, fr.soff, csrc, cn, ch, coff, cout, cdst);
+            child.soff = fr.soff + conv_submit<PREC>(cx, slot, fr.soff, csrc, cn, ch, coff, cout, cdst);
         else if (!pop)
             child.soff = fr.soff;
         if (tid == 0) {
@@ -1715,6 +1720,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
 }
 
 // --------------------------------------------------------------- drivers
+template <int PREC>
 __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
                                                 ll *ret_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
@@ -1775,8 +1781,8 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         if (cx.bnd)
             for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = bin ? i : 2 * i;
         const ll hh = T - 1;
-        conv_submit(cx, SLOT_TOP, 0, src, b + 1, hh, bin ? 0 : hh, 1, dst, beta, tc);
-        conv_wait(cx, SLOT_TOP);
+        conv_submit<PREC>(cx, SLOT_TOP, 0, src, b + 1, hh, bin ? 0 : hh, 1, dst, beta, tc);
+        conv_wait<PREC>(cx, SLOT_TOP);
         if (tid == 0) *val_sh = read_result(dst);
         __syncthreads();
         return *val_sh;
@@ -1806,7 +1812,7 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         if (h > i0) h = i0;
         Frame root{i0, 0, h, b, 0, 0, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        b = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        b = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh);
         if (*cx.err_sh) return NAN;
         i0 -= h;
         double *t = src;
@@ -1818,6 +1824,7 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
     return p;
 }
 
+template <int PREC>
 __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double *rowB, Frame *stk, int *sp_sh,
                                             ll *ret_sh, ll *leaf_sh, ll *red_sh, double *val_sh)
 {
@@ -1862,8 +1869,8 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
             if (cx.bnd)
                 for (ll m = n + 1 + tid; m <= T; m += WG) cx.bnd[m] = NONE;
             const ll hh = T - n;
-            conv_submit(cx, SLOT_TOP, 0, src + L, R - L + 1, hh, hh, 1, dst);
-            conv_wait(cx, SLOT_TOP);
+            conv_submit<PREC>(cx, SLOT_TOP, 0, src + L, R - L + 1, hh, hh, 1, dst);
+            conv_wait<PREC>(cx, SLOT_TOP);
             if (tid == 0) *val_sh = read_result(dst);
             __syncthreads();
             return d.K * (*val_sh);
@@ -1889,11 +1896,11 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
         if (h > T - n) h = T - n;
         // the rest of step n+h, red cells [f+1+h, R-h] from [f+1, R] of step n,
         // is computed while the trapezoid is solved
-        const ll need = conv_submit(cx, SLOT_TOP, 0, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h);
+        const ll need = conv_submit<PREC>(cx, SLOT_TOP, 0, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h);
         Frame root{n, f, h, 0, 0, need, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        const ll fn = solve_trapezoid(cx, root, stk, sp_sh, ret_sh, leaf_sh);
-        conv_wait(cx, SLOT_TOP);
+        const ll fn = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        conv_wait<PREC>(cx, SLOT_TOP);
         if (*cx.err_sh) return NAN;
         n += h;
         R -= h;
@@ -1906,6 +1913,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
 }
 
 // Drive one option (descriptor index o) to its price, with the whole workgroup.
+template <int PREC>
 __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, const double2 *__restrict__ tw,
                                              double *price, ll *bnd, ll bnd_stride, int32_t *err, Stats *stats,
                                              const Pool &pl, const Tune &tn, double2 *lds, const double2 *twl,
@@ -1914,6 +1922,15 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
 {
     const int tid = threadIdx.x;
     char *base = ws + d.ws_off;
+    if (d.prec != PREC) {  // launched with the other precision's kernel
+        if (tid == 0) {
+            price[d.out_index] = NAN;
+            if (err) err[d.out_index] = DEV_RANGE;
+            stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
+        }
+        return;
+    }
     double *rowA = (double *)base;
     double *rowB = rowA + d.row_len;
     double *arena = rowB + d.row_len;
@@ -1946,8 +1963,8 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     __syncthreads();
     const ll ttot = clk();
     double p;
-    if (d.model == BSM) p = drive_bsm(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
-    else p = drive_lattice(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
+    if (d.model == BSM) p = drive_bsm<PREC>(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
+    else p = drive_lattice<PREC>(cx, rowA, rowB, stk, sp_sh, ret_sh, leaf_sh, red_sh, val_sh);
     __syncthreads();
     if (*err_sh) drain(cx);
     if (tid == 0) {
@@ -1965,13 +1982,14 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
 // Persistent solve kernel: options first (one driver workgroup each, claimed
 // in descriptor order), then helping with the published jobs of the drivers
 // still running.
+template <int PREC>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
 solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__restrict__ tw, double *price, ll *bnd,
              ll bnd_stride, int32_t *err, Stats *stats, Pool pl, Tune tn)
 {
     __shared__ double2 lds[NLDS];
     __shared__ double2 twl[NLDS / 2];
-    __shared__ float4 twf[NLDS / 2];
+    __shared__ float4 twf[PREC ? NLDS / 2 : 1];  // split twiddles (mixed precision only)
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
     __shared__ ll ret_sh, leaf_sh, red_sh[WG / 64];
@@ -1983,8 +2001,10 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
     for (int t = tid; t < NLDS / 2; t += WG) {
         const double2 w = tw[(ll)t << (LG_TW - LG_NLDS)];
         twl[t] = w;
-        const CF c = cf_from(w.x, w.y);
-        twf[t] = make_float4(c.rh, c.rl, c.ih, c.il);
+        if (PREC) {
+            const CF c = cf_from(w.x, w.y);
+            twf[t] = make_float4(c.rh, c.rl, c.ih, c.il);
+        }
     }
     for (int t = tid; t < JPW; t += WG) {
         sh.pub[t] = 0;
@@ -2005,12 +2025,12 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
                 __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
             }
         } else {
-            drive_option(d, o, ws, tw, price, bnd, bnd_stride, err, stats, pl, tn, lds, twl, twf, stk, &sp_sh, &err_sh,
+            drive_option<PREC>(d, o, ws, tw, price, bnd, bnd_stride, err, stats, pl, tn, lds, twl, twf, stk, &sp_sh, &err_sh,
                          &ret_sh, &leaf_sh, red_sh, &val_sh, &st_sh, &sh);
         }
         __syncthreads();
     }
-    helper_loop(pl, n, descs, ws, &sh, lds, tw, twl, twf, tn.idle_ticks);
+    helper_loop<PREC>(pl, n, descs, ws, &sh, lds, tw, twl, twf, tn.idle_ticks);
 }
 
 // Clears the pool header, the summary bitmap and the slot words before a launch.
@@ -2055,7 +2075,8 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
     pl.n_wg = n_wg;
     hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((MAX_WG + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        pl.hdr, pl.summary, pl.bits, n_wg);
-    hipLaunchKernelGGL(solve_kernel, dim3((unsigned)n_wg), dim3(WG), 0, (hipStream_t)stream, d_desc, (ll)n, d_ws,
+    auto kern = tune.prec ? solve_kernel<1> : solve_kernel<0>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(WG), 0, (hipStream_t)stream, d_desc, (ll)n, d_ws,
                        (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err,
                        (Stats *)(d_ws + stats_offset(n)), pl, tune);
     return hipGetLastError() == hipSuccess ? 0 : 1;
