@@ -1534,6 +1534,187 @@ __device__ __forceinline__ double read_result(const double *p)
     return __longlong_as_double((long long)v);
 }
 
+// Ordering point for one wave's own LDS and global accesses (its earlier
+// writes complete before its later reads).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// True if every correlation of a trapezoid of height h with n_red red cells
+// (lattices) or boundary-centred width 2h (BSM) is short enough for direct
+// stepping, so that one wave can solve it alone.
+__device__ __forceinline__ bool wave_sized(const Mp &d, const Tune &tn, ll nred, ll h)
+{
+    const ll n = (d.model == BSM) ? 2 * h : nred;
+    return n <= tn.direct_max_n && n <= 1024 && h <= 2 * (ll)tn.direct_max_h;
+}
+
+// Wave-local solve of a small trapezoid (see wave_sized): wave 0 alone walks
+// the frame stages of solve_trapezoid -- first correlation, first
+// sub-trapezoid, second correlation, second sub-trapezoid -- stepping each
+// correlation directly and walking the band at the leaves, with its stack in
+// LDS at wstk (cap frames) and no workgroup barrier.  Returns the boundary of
+// the last row; on a failed check lane 0 records the error in *cx.err_sh.
+__device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk, int cap)
+{
+    const Mp d = cx.p;
+    const int l = threadIdx.x & 63;
+    const int span = (d.model == BINOMIAL) ? 1 : 2;
+    if (l == 0) wstk[0] = root;
+    wave_sync();
+    int sp = 0;
+    ll rv = 0;
+    int e = DEV_OK;
+    while (sp >= 0) {
+        Frame fr = wstk[sp];
+        fr.r0 = uni(fr.r0);
+        fr.c0 = uni(fr.c0);
+        fr.h = uni(fr.h);
+        fr.b = uni(fr.b);
+        fr.aoff = uni(fr.aoff);
+        fr.stage = __builtin_amdgcn_readfirstlane(fr.stage);
+        bool pop = false, leaf = false;
+        Frame child;
+        const double *csrc = nullptr;
+        double *cdst = nullptr;
+        ll cn = 0, ch = 0, coff = 0, cout = 0;
+        if (d.model != BSM) {
+            const ll i0 = fr.r0, c0 = fr.c0, h = fr.h, b = fr.b;
+            const ll h1 = h / 2, h2 = h - h1;
+            const ll nred = b - c0 + 1;
+            if (fr.stage == 0) {
+                if (nred <= BAND) {
+                    if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) e = DEV_RANGE;
+                    else leaf = true;
+                    pop = true;
+                } else {
+                    double *mid = cx.arena + fr.aoff - c0;
+                    if (fr.aoff + nred > cx.arena_len) e = DEV_ARENA;
+                    else if (!in_ws(cx, fr.src, c0, b)) e = DEV_RANGE;
+                    else {
+                        csrc = fr.src + c0;
+                        cn = nred;
+                        ch = h1;
+                        coff = (span == 1) ? 0 : h1;
+                        cout = nred - span * h1;
+                        cdst = mid + c0;
+                        fr.mid = mid;
+                        fr.stage = 1;
+                        child = Frame{i0, b - span * h1 + 1, h1, b, fr.aoff + nred, 0, fr.src, mid, nullptr, 0, 0};
+                    }
+                }
+            } else if (fr.stage == 1) {
+                const ll br = rv;
+                const ll n2 = br - c0 + 1;
+                if (!in_ws(cx, fr.mid, c0, br) || !in_ws(cx, fr.dst, c0, br)) e = DEV_RANGE;
+                else {
+                    csrc = fr.mid + c0;
+                    cn = n2;
+                    ch = h2;
+                    coff = (span == 1) ? 0 : h2;
+                    cout = n2 - span * h2;
+                    cdst = fr.dst + c0;
+                    fr.stage = 2;
+                    child = Frame{i0 - h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst, nullptr,
+                                  0, 0};
+                }
+            } else {
+                pop = true;  // rv: the second sub-trapezoid's boundary
+            }
+        } else {
+            const ll n = fr.r0, f = fr.c0, h = fr.h;
+            const ll h1 = h / 2, h2 = h - h1;
+            if (fr.stage == 0) {
+                if (h <= (BAND - 2) / 2) {
+                    if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) e = DEV_RANGE;
+                    else leaf = true;
+                    pop = true;
+                } else {
+                    const ll base = f - h1 + 1;
+                    double *mid = cx.arena + fr.aoff - base;
+                    if (fr.aoff + 2 * h > cx.arena_len) e = DEV_ARENA;
+                    else if (!in_ws(cx, fr.src, f + 1, f + 2 * h)) e = DEV_RANGE;
+                    else {
+                        csrc = fr.src + f + 1;
+                        cn = 2 * h;
+                        ch = h1;
+                        coff = h1;
+                        cout = 2 * h - 2 * h1;
+                        cdst = mid + f + 1 + h1;
+                        fr.mid = mid;
+                        fr.stage = 1;
+                        child = Frame{n, f, h1, 0, fr.aoff + 2 * h, 0, fr.src, mid, nullptr, 0, 0};
+                    }
+                }
+            } else if (fr.stage == 1) {
+                const ll fp = rv;
+                const ll nin = f + h + h2 - fp;
+                if (fp < f - h1 || fp > f) e = DEV_RANGE;
+                else if (!in_ws(cx, fr.mid, fp + 1, f + h + h2) || !in_ws(cx, fr.dst, fp + 1 + h2, f + h)) e = DEV_RANGE;
+                else {
+                    csrc = fr.mid + fp + 1;
+                    cn = nin;
+                    ch = h2;
+                    coff = h2;
+                    cout = nin - 2 * h2;
+                    cdst = fr.dst + fp + 1 + h2;
+                    fr.stage = 2;
+                    child = Frame{n + h1, fp, h2, 0, fr.aoff + 2 * h, 0, fr.mid, fr.dst, nullptr, 0, 0};
+                }
+            } else {
+                pop = true;
+            }
+        }
+        if (e != DEV_OK) break;
+        if (leaf) {
+            const ll tb = clk();
+            if (d.model == BINOMIAL) rv = band_bin(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
+            else if (d.model == TRINOMIAL) rv = band_tri(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
+            else rv = band_bsm(d, fr.r0, fr.c0, fr.h, fr.c0 + 2 * fr.h, fr.src, fr.dst, cx.bnd, nullptr);
+            rv = uni(rv);
+            if (l == 0) {
+                cx.st->band_rows += fr.h;
+                cx.st->cyc_band += clk() - tb;
+            }
+        }
+        if (!pop && cout > 0) {
+            // the stage's correlation, stepped directly by this wave
+            const ll tb = clk();
+            if (cn <= 128) direct_wave<2>(d, csrc, cn, ch, coff, cout, cdst);
+            else if (cn <= 256) direct_wave<4>(d, csrc, cn, ch, coff, cout, cdst);
+            else if (cn <= 512) direct_wave<8>(d, csrc, cn, ch, coff, cout, cdst);
+            else direct_wave<16>(d, csrc, cn, ch, coff, cout, cdst);
+            if (l == 0) {
+                Stats *st = cx.st;
+                const int lg = ceil_log2(cn);
+                st->convs += 1;
+                st->conv_in += cn;
+                st->conv_out += cout;
+                st->fft_points += ll(1) << (lg < 1 ? 1 : lg);
+                st->n_direct += 1;
+                st->cyc_tiles += clk() - tb;
+            }
+        }
+        if (pop) {
+            --sp;
+        } else if (sp + 1 >= cap) {
+            e = DEV_STACK;
+            break;
+        } else {
+            if (l == 0) {
+                wstk[sp] = fr;
+                wstk[sp + 1] = child;
+            }
+            ++sp;
+        }
+        wave_sync();
+    }
+    if (e != DEV_OK && l == 0 && *cx.err_sh == 0) *cx.err_sh = e;
+    return rv;
+}
+
 // Solve one trapezoid (model-dependent geometry, see the frame stages below)
 // and return the boundary of its last row.  All lanes call it; control flow is
 // uniform.  A frame at depth s keeps its correlations in job slot s + 1: the
@@ -1583,9 +1764,8 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll h1 = h / 2, h2 = h - h1;
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
-                if (nred <= BAND) {
-                    if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) e = DEV_RANGE;
-                    else leaf = true;
+                if (nred <= BAND || wave_sized(d, cx.tn, nred, h)) {
+                    leaf = true;  // wave 0 solves it alone (band, or direct steps and bands)
                     pop = true;
                 } else {
                     // (1) row r = i0 - h1, columns [c0, b - span h1], by correlation from row i0.
@@ -1633,9 +1813,8 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll n = fr.r0, f = fr.c0, h = fr.h;
             const ll h1 = h / 2, h2 = h - h1;
             if (fr.stage == 0) {
-                if (h <= (BAND - 2) / 2) {
-                    if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) e = DEV_RANGE;
-                    else leaf = true;
+                if (h <= (BAND - 2) / 2 || wave_sized(d, cx.tn, 2 * h, h)) {
+                    leaf = true;  // wave 0 solves it alone
                     pop = true;
                 } else {
                     // middle step n+h1 on [f-h1+1, f+h+h2] (2h cells)
@@ -1678,17 +1857,11 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             }
         }
         if (leaf) {
-            const ll tb = clk();
             if (tid < 64) {
-                ll r;
-                if (d.model == BINOMIAL) r = band_bin(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
-                else if (d.model == TRINOMIAL) r = band_tri(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
-                else r = band_bsm(d, fr.r0, fr.c0, fr.h, fr.c0 + 2 * fr.h, fr.src, fr.dst, cx.bnd, nullptr);
-                if (tid == 0) {
-                    *leaf_sh = r;
-                    cx.st->band_rows += fr.h;
-                    cx.st->cyc_band += clk() - tb;
-                }
+                Frame w = fr;
+                w.stage = 0;
+                const ll r = wave_solve(cx, w, stk + s + 1, MAXD - s - 1);
+                if (tid == 0) *leaf_sh = r;
             }
             __syncthreads();
             result = *leaf_sh;
