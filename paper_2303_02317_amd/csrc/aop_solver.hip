@@ -1194,7 +1194,30 @@ __device__ __forceinline__ void fetch_args(const Pool &pl, int ji, JobArgs *sh)
 }
 
 // Per-workgroup LDS state shared by the driver and helper roles.
+// Queue through which the wave that solves a small trapezoid hands its
+// direct-stepping correlations to the workgroup's other waves (all in LDS).
+// A frame has at most one outstanding correlation, kept in the job slot of
+// its stack depth until the frame has waited for it; tickets (numbered in
+// push order) say which slot to run next, so the unclaimed tickets never
+// outnumber the frames on the stack.
+#define WQ 16  // job slots = deepest stack; also the ticket ring size
+struct WJob {
+    const double *src;
+    double *dst;
+    ll n_in, h, out_off, n_out;
+};
+struct WQueue {
+    WJob job[WQ];
+    int done[WQ];    // slot's job finished: done[slot] == its ticket + 1
+    int ticket[WQ];  // ticket k names slot ticket[k % WQ]
+    int head;        // next ticket to claim
+    int tail;        // tickets issued
+    int quit;        // the pushing wave has finished
+    int pad;
+};
+
 struct Shared {
+    WQueue wq;
     int msg, ji, opt, pad;
     JobArgs args;          // arguments of the tile a helper claimed
     JobArgs jargs[JPW];    // arguments of each slot's pending job (driver)
@@ -1551,20 +1574,122 @@ __device__ __forceinline__ bool wave_sized(const Mp &d, const Tune &tn, ll nred,
     return n <= tn.direct_max_n && n <= 1024 && h <= 2 * (ll)tn.direct_max_h;
 }
 
+#define WGS __HIP_MEMORY_SCOPE_WORKGROUP
+
+// One direct-stepping correlation by the calling wave.
+__device__ __forceinline__ void run_direct(const Mp &d, const WJob &j)
+{
+    if (j.n_in <= 128) direct_wave<2>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+    else if (j.n_in <= 256) direct_wave<4>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+    else if (j.n_in <= 512) direct_wave<8>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+    else direct_wave<16>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+}
+
+// Claim the next unclaimed ticket (one wave; -1 if none).
+__device__ __forceinline__ int wq_claim(WQueue *q)
+{
+    int k = -1;
+    if ((threadIdx.x & 63) == 0) {
+        const int t = __hip_atomic_load(&q->tail, __ATOMIC_ACQUIRE, WGS);
+        int h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, WGS);
+        while (h < t) {
+            if (__hip_atomic_compare_exchange_strong(&q->head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED, WGS)) {
+                k = h;
+                break;
+            }
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(k);
+}
+
+// Run the job of claimed ticket k and mark it done (its global writes complete first).
+__device__ __forceinline__ void wq_run(const Mp &d, WQueue *q, int k)
+{
+    const int slot = __builtin_amdgcn_readfirstlane(q->ticket[k % WQ]);
+    WJob j = q->job[slot];
+    j.n_in = uni(j.n_in);
+    j.h = uni(j.h);
+    j.out_off = uni(j.out_off);
+    j.n_out = uni(j.n_out);
+    run_direct(d, j);
+    wave_sync();
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&q->done[slot], k + 1, __ATOMIC_RELEASE, WGS);
+}
+
+// A helper wave of a small-trapezoid solve: run queued correlations until the
+// solving wave has finished (or a deadline passes).
+__device__ __forceinline__ void wq_worker(const Mp &d, WQueue *q, ll timeout_ticks)
+{
+    ll last = now_ticks();
+    for (;;) {
+        const int k = wq_claim(q);
+        if (k >= 0) {
+            wq_run(d, q, k);
+            last = now_ticks();
+            continue;
+        }
+        int stop = 0;
+        if ((threadIdx.x & 63) == 0) {
+            stop = __hip_atomic_load(&q->quit, __ATOMIC_ACQUIRE, WGS) &&
+                   __hip_atomic_load(&q->head, __ATOMIC_RELAXED, WGS) >= __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, WGS);
+            if (now_ticks() - last > timeout_ticks) stop = 1;
+        }
+        if (__builtin_amdgcn_readfirstlane(stop)) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Push the job of stack slot `slot` (the solving wave); returns its ticket.
+__device__ __forceinline__ int wq_push(WQueue *q, int slot, const WJob &j, int *tail)
+{
+    const int k = *tail;
+    if ((threadIdx.x & 63) == 0) {
+        q->job[slot] = j;
+        q->ticket[k % WQ] = slot;
+    }
+    wave_sync();  // the entry and this wave's row writes precede the publication
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&q->tail, k + 1, __ATOMIC_RELEASE, WGS);
+    *tail = k + 1;
+    return k;
+}
+
+// Wait for the job of slot `slot`, ticket k (the solving wave), running
+// unclaimed jobs meanwhile.
+__device__ __forceinline__ bool wq_wait(const Mp &d, WQueue *q, int slot, int k, ll timeout_ticks, Stats *st)
+{
+    const ll t0 = now_ticks();
+    for (;;) {
+        int fin = 0;
+        if ((threadIdx.x & 63) == 0) fin = __hip_atomic_load(&q->done[slot], __ATOMIC_ACQUIRE, WGS) == k + 1;
+        if (__builtin_amdgcn_readfirstlane(fin)) return true;
+        const int c = wq_claim(q);
+        if (c >= 0) {
+            const ll tb = clk();
+            wq_run(d, q, c);
+            if ((threadIdx.x & 63) == 0) st->cyc_tiles += clk() - tb;
+            continue;
+        }
+        if (now_ticks() - t0 > timeout_ticks) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Wave-local solve of a small trapezoid (see wave_sized): wave 0 alone walks
 // the frame stages of solve_trapezoid -- first correlation, first
 // sub-trapezoid, second correlation, second sub-trapezoid -- stepping each
 // correlation directly and walking the band at the leaves, with its stack in
 // LDS at wstk (cap frames) and no workgroup barrier.  Returns the boundary of
 // the last row; on a failed check lane 0 records the error in *cx.err_sh.
-__device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk, int cap)
+__device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk, int cap, WQueue *q)
 {
     const Mp d = cx.p;
     const int l = threadIdx.x & 63;
     const int span = (d.model == BINOMIAL) ? 1 : 2;
+    const ll timeout = cx.tn.timeout_ticks;
+    if (cap > WQ) cap = WQ;  // one outstanding correlation per frame fits the queue
     if (l == 0) wstk[0] = root;
     wave_sync();
-    int sp = 0;
+    int sp = 0, tail = 0;
     ll rv = 0;
     int e = DEV_OK;
     while (sp >= 0) {
@@ -1574,7 +1699,17 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
         fr.h = uni(fr.h);
         fr.b = uni(fr.b);
         fr.aoff = uni(fr.aoff);
+        fr.soff = uni(fr.soff);
         fr.stage = __builtin_amdgcn_readfirstlane(fr.stage);
+        // the frame's pending correlation (job index + 1 in soff) must be done
+        // before its next stage reads its output
+        if (fr.soff > 0) {
+            if (!wq_wait(d, q, sp, (int)fr.soff - 1, timeout, cx.st)) {
+                e = DEV_TIMEOUT;
+                break;
+            }
+            fr.soff = 0;
+        }
         bool pop = false, leaf = false;
         Frame child;
         const double *csrc = nullptr;
@@ -1680,12 +1815,16 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             }
         }
         if (!pop && cout > 0) {
-            // the stage's correlation, stepped directly by this wave
-            const ll tb = clk();
-            if (cn <= 128) direct_wave<2>(d, csrc, cn, ch, coff, cout, cdst);
-            else if (cn <= 256) direct_wave<4>(d, csrc, cn, ch, coff, cout, cdst);
-            else if (cn <= 512) direct_wave<8>(d, csrc, cn, ch, coff, cout, cdst);
-            else direct_wave<16>(d, csrc, cn, ch, coff, cout, cdst);
+            // the stage's correlation goes to the other waves while this one
+            // solves the sub-trapezoid that does not depend on it
+            WJob j;
+            j.src = csrc;
+            j.dst = cdst;
+            j.n_in = cn;
+            j.h = ch;
+            j.out_off = coff;
+            j.n_out = cout;
+            fr.soff = wq_push(q, sp, j, &tail) + 1;
             if (l == 0) {
                 Stats *st = cx.st;
                 const int lg = ceil_log2(cn);
@@ -1694,7 +1833,6 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
                 st->conv_out += cout;
                 st->fft_points += ll(1) << (lg < 1 ? 1 : lg);
                 st->n_direct += 1;
-                st->cyc_tiles += clk() - tb;
             }
         }
         if (pop) {
@@ -1710,6 +1848,13 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             ++sp;
         }
         wave_sync();
+    }
+    if (e != DEV_OK && e != DEV_TIMEOUT) {
+        // finish the outstanding jobs of the frames still on the stack
+        for (int k = sp; k >= 0; --k) {
+            const ll so = uni(wstk[k].soff);
+            if (so > 0 && !wq_wait(d, q, k, (int)so - 1, timeout, cx.st)) break;
+        }
     }
     if (e != DEV_OK && l == 0 && *cx.err_sh == 0) *cx.err_sh = e;
     return rv;
@@ -1857,11 +2002,26 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             }
         }
         if (leaf) {
+            WQueue *q = &cx.sh->wq;
+            if (tid == 0) {
+                q->head = 0;
+                q->tail = 0;
+                q->quit = 0;
+                for (int k = 0; k < WQ; ++k) q->done[k] = -1;
+            }
+            __syncthreads();
             if (tid < 64) {
+                // wave 0 solves; waves 1..3 step the correlations it queues
                 Frame w = fr;
                 w.stage = 0;
-                const ll r = wave_solve(cx, w, stk + s + 1, MAXD - s - 1);
-                if (tid == 0) *leaf_sh = r;
+                w.soff = 0;
+                const ll r = wave_solve(cx, w, stk + s + 1, MAXD - s - 1, q);
+                if (tid == 0) {
+                    *leaf_sh = r;
+                    __hip_atomic_store(&q->quit, 1, __ATOMIC_RELEASE, WGS);
+                }
+            } else {
+                wq_worker(d, q, cx.tn.timeout_ticks);
             }
             __syncthreads();
             result = *leaf_sh;
