@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving mix timed after the batch (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer twice (reference kernel for HBM byte counters)")
     ap.add_argument("--plain", action="store_true",
                     help="also time the plain Theta(T^2) GPU stencil on the same batch (one step)")
     args = ap.parse_args()
@@ -165,6 +167,17 @@ def main():
     import torch
 
     from paper_2303_02317_amd import binding, inputs
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        x = torch.full((nbytes // 8,), 1.0, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 2}), flush=True)
+        return
 
     model = TYPES[args.option_type]
     opts = inputs.batch(CONFIG_ID[model], args.log2T, args.options, model)

@@ -176,6 +176,13 @@ typedef struct {
  * n entries; entries of rejected options are zero. */
 aop_status aop_batch_stats(const void *d_workspace, int64_t n, aop_stats *h_stats);
 
+/* Device-side error code of each option of the last aop_price_batch (or graph
+ * replay) on this workspace, in the caller's order (synchronous): 0 none,
+ * 1 a range check failed, 2 recursion stack, 3 arena or FFT scratch exhausted,
+ * 5 a wait passed its deadline, 6 priced after the launch aborted.  An option
+ * with a nonzero code has a NaN price. */
+aop_status aop_batch_errors(const void *d_workspace, int64_t n, int32_t *h_err);
+
 /* Work-pool counters of the last aop_price_batch on this workspace
  * (synchronous): h_out[0] workgroups, [1] tiles computed by helper
  * workgroups, [2] helper busy cycles, [3] helper idle cycles, [4] options

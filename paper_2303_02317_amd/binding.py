@@ -27,7 +27,7 @@ EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_vali
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
            "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
            "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
-           "aop_graph_create", "aop_graph_launch", "aop_graph_destroy"]
+           "aop_graph_create", "aop_graph_launch", "aop_graph_destroy", "aop_batch_errors"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
                 "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
@@ -107,6 +107,7 @@ def load():
         "aop_graph_create": (I32, [P, P, I64, I32, P, SZ, P, P, P, I64, ctypes.POINTER(P)]),
         "aop_graph_launch": (I32, [P, P]),
         "aop_graph_destroy": (I32, [P]),
+        "aop_batch_errors": (I32, [P, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -269,6 +270,14 @@ def batch_stats(launch: "Launch", n: int) -> np.ndarray:
     out = np.zeros((max(n, 1), len(STATS_FIELDS)), dtype=np.int64)
     _check(load().aop_batch_stats(ctypes.c_void_p(launch.workspace.data_ptr()), n,
                                   out.ctypes.data_as(ctypes.c_void_p)), "aop_batch_stats")
+    return out[:n]
+
+
+def batch_errors(launch, n: int) -> np.ndarray:
+    """Device error code of each option of a finished launch (0: none)."""
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    _check(load().aop_batch_errors(ctypes.c_void_p(launch.workspace.data_ptr()), n,
+                                   out.ctypes.data_as(ctypes.c_void_p)), "aop_batch_errors")
     return out[:n]
 
 

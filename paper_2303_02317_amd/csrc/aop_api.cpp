@@ -527,6 +527,15 @@ aop_status aop_batch_stats(const void *d_ws, int64_t n, aop_stats *h_stats)
                : AOP_EDEVICE;
 }
 
+aop_status aop_batch_errors(const void *d_ws, int64_t n, int32_t *h_err)
+{
+    if (!d_ws || !h_err || n < 0) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    const char *src = (const char *)d_ws + aop::err_offset(n);
+    return hipMemcpy(h_err, src, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost) == hipSuccess ? AOP_OK
+                                                                                                  : AOP_EDEVICE;
+}
+
 aop_status aop_pool_stats(const void *d_ws, int64_t n, int64_t *h_out)
 {
     if (!d_ws || !h_out || n < 0) return AOP_EINVAL;

@@ -63,10 +63,12 @@ constexpr int64_t POOL_SUMMARY = 128;                 // byte offset of the summ
 constexpr int64_t POOL_BITS = 256;                    // byte offset of the per-workgroup slot words
 constexpr int64_t POOL_JOBS = POOL_BITS + 8 * MAX_WG; // byte offset of the job slots
 constexpr int64_t POOL_BYTES = POOL_JOBS + JOB_BYTES * JPW * MAX_WG;
-inline int64_t pool_offset(int64_t n)
+// Per-option device error codes (DevErr, int32) after the counters.
+inline int64_t err_offset(int64_t n)
 {
     return stats_offset(n) + ((int64_t)128 * (n > 0 ? n : 1) + 255) / 256 * 256;
 }
+inline int64_t pool_offset(int64_t n) { return err_offset(n) + ((int64_t)4 * (n > 0 ? n : 1) + 255) / 256 * 256; }
 inline int64_t options_offset(int64_t n) { return pool_offset(n) + POOL_BYTES; }
 
 // Launch-time tuning of the solve kernel (device clock units).

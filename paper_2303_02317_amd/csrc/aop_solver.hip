@@ -142,7 +142,7 @@ __device__ ll block_max(ll v, ll *sh)
 // Inverse (unnormalised): decimation in time, bit-reversed in -> natural out.
 // Each pass loads 2^K elements per lane, applies K radix-2 stages in
 // registers and stores them back, so a 2048-point transform takes four LDS
-// round trips.  twl holds e^{-2 pi i t / 2048}, t < 1024.
+// round trips.  twl holds e^{-2 pi i t / 4096}, t <= 2048 (LDS).
 template <int K, bool INV>
 __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, const double2 *twl)
 {
@@ -169,7 +169,7 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
                 for (int q = 0; q < G; ++q) {
                     if (q & (1 << t)) continue;
                     const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
-                    const double2 w = twl[jj << (10 - s)];
+                    const double2 w = twl[jj << (11 - s)];
                     const double2 u = v[q], z = v[q + (1 << t)];
                     v[q] = make_double2(u.x + z.x, u.y + z.y);
                     v[q + (1 << t)] = cmul(make_double2(u.x - z.x, u.y - z.y), w);
@@ -183,7 +183,7 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
                 for (int q = 0; q < G; ++q) {
                     if (q & (1 << t)) continue;
                     const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
-                    const double2 w = twl[jj << (10 - s)];
+                    const double2 w = twl[jj << (11 - s)];
                     const double2 u = v[q], z = cmulc(v[q + (1 << t)], w);
                     v[q] = make_double2(u.x + z.x, u.y + z.y);
                     v[q + (1 << t)] = make_double2(u.x - z.x, u.y - z.y);
@@ -440,13 +440,43 @@ __device__ __forceinline__ Spec make_spec(const Mp &p, ll h, double beta, double
     return q;
 }
 
-__device__ __forceinline__ double2 kernel_power(const Spec &q, ll f, int lgN, const double2 *__restrict__ tw)
+// Trig values of a bin from the LDS table (e^{-2 pi i t / 4096}, t <= 2048).
+__device__ __forceinline__ double2 twl_at(const double2 *twl, int t)  // any t in [0, 4096)
 {
-    const double2 e = tw[f << (LG_TW - lgN)];  // e^{-i theta}, theta = 2 pi f / N
-    const double cs = e.x, sn = -e.y;
-    double sh;
-    if (lgN < LG_TW) sh = tw[f << (LG_TW - 1 - lgN)].y;  // -sin(theta/2)
-    else sh = sinpi((double)f / (double)(ll(1) << lgN));
+    if (t <= 2048) return twl[t];
+    const double2 w = twl[t - 2048];  // e^{-i pi} e^{-2 pi i (t - 2048) / 4096}
+    return make_double2(-w.x, -w.y);
+}
+// Bin f of a transform of 2^lgN <= 2048 points: theta = 2 pi f / N, f <= N / 2.
+__device__ __forceinline__ void bin_trig_lds(const double2 *twl, ll f, int lgN, double &cs, double &sn, double &sh)
+{
+    const double2 e = twl[f << (12 - lgN)];
+    cs = e.x;
+    sn = -e.y;
+    sh = twl[f << (11 - lgN)].y;
+}
+// Bin k1 + N1 k2 of a four-step transform (N = N1 * 2048): r1 = e^{-2 pi i k1/N}
+// and r2 = e^{-i pi k1/N} are the tile's row factors, the rest comes from LDS.
+__device__ __forceinline__ void bin_trig_rows(const double2 *twl, double2 r1, double2 r2, int k2, double &cs,
+                                              double &sn, double &sh)
+{
+    const double2 a = twl_at(twl, 2 * k2);
+    const double2 e = cmul(r1, a);
+    cs = e.x;
+    sn = -e.y;
+    sh = cmul(r2, twl[k2]).y;
+}
+// e^{-2 pi i m / N}, m < N (four-step column twiddles), by sincospi in FP64.
+__device__ __forceinline__ double2 twiddle_n(ll m, int lgN)
+{
+    double sv, cv;
+    sincospi((double)(2 * m) / (double)(ll(1) << lgN), &sv, &cv);
+    return make_double2(cv, -sv);
+}
+
+// cs, sn: cos and sin of theta; sh: +-sin(theta/2) (only its square is used).
+__device__ __forceinline__ double2 kernel_power(const Spec &q, double cs, double sn, double sh)
+{
     const double s = sh * sh;  // sin^2(theta/2)
     double delta, arg;
     if (q.bin) {
@@ -537,7 +567,9 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     lds_dif(lds, lgN, 1, twl);
     // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
     for (ll f = tid; f <= N / 2; f += WG) {
-        const double2 m = kernel_power(q, f, lgN, tw);
+        double cs, sn, sh;
+        bin_trig_lds(twl, f, lgN, cs, sn, sh);
+        const double2 m = kernel_power(q, cs, sn, sh);
         const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
         lds[t1] = cmul(lds[t1], m);
         if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
@@ -554,7 +586,6 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
     const int N1 = 1 << lg1, C = NLDS >> lg1;
-    const int twsh = LG_TW - lgN;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
     for (int t = tid; t < NLDS; t += WG) {
@@ -567,7 +598,7 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t % C, p1 = t / C;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
         j.scr[(ll)p1 * N2 + n2] = cmul(lds[c * N1 + p1], w);
     }
     __syncthreads();
@@ -578,7 +609,6 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N2 = ll(1) << lg2;
-    const int N1 = 1 << lg1;
     const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
     const int tid = threadIdx.x;
     const int p1 = tile;
@@ -587,9 +617,16 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     for (int t = tid; t < N2; t += WG) lds[t] = row[t];
     __syncthreads();
     lds_dif(lds, lg2, 1, twl);
+    double sr, cr;
+    sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
+    const double2 r1 = make_double2(cr, -sr);
+    sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
+    const double2 r2 = make_double2(cr, -sr);
     for (int t = tid; t < N2; t += WG) {
-        const ll k2 = bitrev(t, lg2);
-        lds[t] = cmul(lds[t], kernel_power(q, k1 + (ll)N1 * k2, lgN, tw));
+        const int k2 = (int)bitrev(t, lg2);
+        double cs, sn, sh;
+        bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
+        lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
     }
     __syncthreads();
     lds_dit_inv(lds, lg2, 1, twl);
@@ -603,14 +640,13 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
     const int N1 = 1 << lg1, C = NLDS >> lg1;
-    const int twsh = LG_TW - lgN;
     const double invN = 1.0 / (double)N;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t % C, p1 = t / C;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
         lds[c * N1 + p1] = cmulc(j.scr[(ll)p1 * N2 + n2], w);
     }
     __syncthreads();
@@ -640,7 +676,7 @@ __device__ __forceinline__ CF cf_scale64c(const CF &a, double2 m)  // split(a * 
     return cf_from(x.x * m.x + x.y * m.y, x.y * m.x - x.x * m.y);
 }
 
-__device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float4 *lds, const double2 *__restrict__ tw,
+__device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float4 *lds, const double2 *twl,
                                             const float4 *twf)
 {
     const int lgN = j.lgN;
@@ -652,7 +688,9 @@ __device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float
     __syncthreads();
     lds_dif_ff(lds, lgN, 1, twf);
     for (ll f = tid; f <= N / 2; f += WG) {
-        const double2 m = kernel_power(q, f, lgN, tw);
+        double cs, sn, sh;
+        bin_trig_lds(twl, f, lgN, cs, sn, sh);
+        const double2 m = kernel_power(q, cs, sn, sh);
         const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
         st_cf(lds + t1, cf_scale64(ld_cf(lds + t1), m));
         if (t2 != t1) st_cf(lds + t2, cf_scale64c(ld_cf(lds + t2), m));
@@ -672,7 +710,6 @@ __device__ __forceinline__ void tile_col_fwd_ff(const JobArgs &j, int tile, floa
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
     const int N1 = 1 << lg1, C = NLDS >> lg1;
-    const int twsh = LG_TW - lgN;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
     float4 *scr = (float4 *)j.scr;
@@ -686,18 +723,17 @@ __device__ __forceinline__ void tile_col_fwd_ff(const JobArgs &j, int tile, floa
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t % C, p1 = t / C;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
         st_cf(scr + (ll)p1 * N2 + n2, cf_scale64(ld_cf(lds + c * N1 + p1), w));
     }
     __syncthreads();
 }
 
 __device__ __forceinline__ void tile_rows_ff(const Mp &p, const JobArgs &j, int tile, float4 *lds,
-                                             const double2 *__restrict__ tw, const float4 *twf)
+                                             const double2 *twl, const float4 *twf)
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N2 = ll(1) << lg2;
-    const int N1 = 1 << lg1;
     const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
     const int tid = threadIdx.x;
     const int p1 = tile;
@@ -706,9 +742,16 @@ __device__ __forceinline__ void tile_rows_ff(const Mp &p, const JobArgs &j, int 
     for (int t = tid; t < N2; t += WG) lds[t] = row[t];
     __syncthreads();
     lds_dif_ff(lds, lg2, 1, twf);
+    double sr, cr;
+    sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
+    const double2 r1 = make_double2(cr, -sr);
+    sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
+    const double2 r2 = make_double2(cr, -sr);
     for (int t = tid; t < N2; t += WG) {
-        const ll k2 = bitrev(t, lg2);
-        st_cf(lds + t, cf_scale64(ld_cf(lds + t), kernel_power(q, k1 + (ll)N1 * k2, lgN, tw)));
+        const int k2 = (int)bitrev(t, lg2);
+        double cs, sn, sh;
+        bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
+        st_cf(lds + t, cf_scale64(ld_cf(lds + t), kernel_power(q, cs, sn, sh)));
     }
     __syncthreads();
     lds_dit_inv_ff(lds, lg2, 1, twf);
@@ -722,7 +765,6 @@ __device__ __forceinline__ void tile_col_inv_ff(const JobArgs &j, int tile, floa
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
     const int N1 = 1 << lg1, C = NLDS >> lg1;
-    const int twsh = LG_TW - lgN;
     const double invN = 1.0 / (double)N;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
@@ -730,7 +772,7 @@ __device__ __forceinline__ void tile_col_inv_ff(const JobArgs &j, int tile, floa
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t % C, p1 = t / C;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = tw[((n2 * k1) & (N - 1)) << twsh];
+        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
         st_cf(lds + c * N1 + p1, cf_scale64c(ld_cf(scr + (ll)p1 * N2 + n2), w));
     }
     __syncthreads();
@@ -819,9 +861,9 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
         __syncthreads();
     } else if (PREC) {
         float4 *l4 = (float4 *)lds;
-        if (j.kind == K_LDS) tile_lds_ff(p, j, l4, tw, twf);
+        if (j.kind == K_LDS) tile_lds_ff(p, j, l4, twl, twf);
         else if (ph == 0) tile_col_fwd_ff(j, t, l4, tw, twf);
-        else if (ph == 1) tile_rows_ff(p, j, t, l4, tw, twf);
+        else if (ph == 1) tile_rows_ff(p, j, t, l4, twl, twf);
         else tile_col_inv_ff(j, t, l4, tw, twf);
     } else if (j.kind == K_LDS) {
         tile_lds(p, j, lds, tw, twl);
@@ -2321,7 +2363,7 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
              ll bnd_stride, int32_t *err, Stats *stats, Pool pl, Tune tn)
 {
     __shared__ double2 lds[NLDS];
-    __shared__ double2 twl[NLDS / 2];
+    __shared__ double2 twl[NLDS + 1];  // e^{-2 pi i t / 4096}, t <= 2048
     __shared__ float4 twf[PREC ? NLDS / 2 : 1];  // split twiddles (mixed precision only)
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
@@ -2331,10 +2373,10 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
     __shared__ Shared sh;
 
     const int tid = threadIdx.x;
-    for (int t = tid; t < NLDS / 2; t += WG) {
-        const double2 w = tw[(ll)t << (LG_TW - LG_NLDS)];
-        twl[t] = w;
-        if (PREC) {
+    for (int t = tid; t <= NLDS; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS - 1)];
+    if (PREC) {
+        for (int t = tid; t < NLDS / 2; t += WG) {
+            const double2 w = tw[(ll)t << (LG_TW - LG_NLDS)];  // e^{-2 pi i t / 2048}
             const CF c = cf_from(w.x, w.y);
             twf[t] = make_float4(c.rh, c.rl, c.ih, c.il);
         }
@@ -2354,6 +2396,7 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
         if (d.model < 0) {  // rejected on the host: no work, price NaN
             if (tid == 0) {
                 price[d.out_index] = NAN;
+                if (err) err[d.out_index] = DEV_OK;
                 stats[d.out_index] = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
                 __hip_atomic_fetch_add((unsigned long long *)&pl.hdr->status, 1ull, __ATOMIC_RELEASE, AGENT);
             }
@@ -2366,14 +2409,19 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
     helper_loop<PREC>(pl, n, descs, ws, &sh, lds, tw, twl, twf, tn.idle_ticks);
 }
 
-// Clears the pool header, the summary bitmap and the slot words before a launch.
+// Clears the pool header, the summary bitmap and the slot words before a
+// launch.  The solve kernel reads these words only with atomic
+// read-modify-writes, so they are cleared with atomic exchanges too: the
+// clearing must be visible to those atomics even where consecutive kernels of a
+// captured graph run without the cache maintenance separate launches get.
 __global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsigned long long *bits, int n_wg)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < 16) ((int64_t *)hdr)[t] = 0;
-    if (t == 0) hdr->n_wg = (uint32_t)n_wg;
-    if (t < MAX_WG / 64) summary[t] = 0ull;
-    if (t < n_wg) bits[t] = 0ull;
+    unsigned long long *h64 = (unsigned long long *)hdr;
+    if (t == 0) __hip_atomic_exchange(h64, (unsigned long long)(unsigned)n_wg << 32, __ATOMIC_RELAXED, AGENT);
+    else if (t < 16) __hip_atomic_exchange(h64 + t, 0ull, __ATOMIC_RELAXED, AGENT);
+    if (t < MAX_WG / 64) __hip_atomic_exchange(summary + t, 0ull, __ATOMIC_RELAXED, AGENT);
+    if (t < n_wg) __hip_atomic_exchange(bits + t, 0ull, __ATOMIC_RELAXED, AGENT);
 }
 
 __global__ void twiddle_kernel(double2 *tw)
@@ -2409,6 +2457,7 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
     hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((MAX_WG + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        pl.hdr, pl.summary, pl.bits, n_wg);
     auto kern = tune.prec ? solve_kernel<1> : solve_kernel<0>;
+    if (!d_err) d_err = (int32_t *)(d_ws + err_offset(n));
     hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(WG), 0, (hipStream_t)stream, d_desc, (ll)n, d_ws,
                        (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err,
                        (Stats *)(d_ws + stats_offset(n)), pl, tune);
