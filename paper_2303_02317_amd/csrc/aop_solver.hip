@@ -221,6 +221,95 @@ __device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl)
     }
 }
 
+// Single transforms of 2^lg <= 2048 points in the same pass structure (radix
+// 8 from the top for the forward transform, from the bottom for the
+// inverse), without the batch bookkeeping of lds_pass: a radix-2^K pass over
+// stages slo+K-1 .. slo reads the K twiddles W_{2^{s+1}}^j of its group from
+// the table; the butterflies' remaining factors are powers of W_8, applied as
+// constants.
+__device__ __forceinline__ double2 rot_w8(double2 d, int e, bool cj)  // d * W_8^e (or conj), e < 4
+{
+    constexpr double R = 0.70710678118654752440;
+    if (e == 0) return d;
+    if (!cj) {
+        if (e == 2) return make_double2(d.y, -d.x);
+        if (e == 1) return make_double2((d.x + d.y) * R, (d.y - d.x) * R);
+        return make_double2((d.y - d.x) * R, -(d.x + d.y) * R);
+    }
+    if (e == 2) return make_double2(-d.y, d.x);
+    if (e == 1) return make_double2((d.x - d.y) * R, (d.x + d.y) * R);
+    return make_double2(-(d.x + d.y) * R, (d.x - d.y) * R);
+}
+
+template <int K, bool INV>
+__device__ __forceinline__ void cpass(double2 *x, int lg, int slo, const double2 *twl)
+{
+    constexpr int G = 1 << K;
+    const int per = (1 << lg) >> K;
+    const int jm = (1 << slo) - 1;
+    for (int gi = threadIdx.x; gi < per; gi += WG) {
+        const int j = gi & jm;
+        const int base = ((gi >> slo) << (slo + K)) + j;
+        double2 v[G], w[K];
+#pragma unroll
+        for (int q = 0; q < G; ++q) v[q] = x[base + (q << slo)];
+#pragma unroll
+        for (int t = 0; t < K; ++t) w[t] = twl[j << (11 - (slo + t))];
+        if (!INV) {
+#pragma unroll
+            for (int t = K - 1; t >= 0; --t) {
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const double2 u = v[q], z = v[q + (1 << t)];
+                    v[q] = make_double2(u.x + z.x, u.y + z.y);
+                    const double2 d = rot_w8(make_double2(u.x - z.x, u.y - z.y), (q & ((1 << t) - 1)) << (2 - t), false);
+                    v[q + (1 << t)] = cmul(d, w[t]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (q & (1 << t)) continue;
+                    const double2 u = v[q];
+                    const double2 z = rot_w8(cmulc(v[q + (1 << t)], w[t]), (q & ((1 << t) - 1)) << (2 - t), true);
+                    v[q] = make_double2(u.x + z.x, u.y + z.y);
+                    v[q + (1 << t)] = make_double2(u.x - z.x, u.y - z.y);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) x[base + (q << slo)] = v[q];
+    }
+    __syncthreads();
+}
+
+// Forward (natural order in, bit-reversed out) and unnormalised inverse
+// (bit-reversed in, natural out) transforms of 2^lg points.
+__device__ __forceinline__ void dif1(double2 *x, int lg, const double2 *twl)
+{
+    for (int shi = lg - 1; shi >= 0;) {
+        const int k = shi + 1 >= 3 ? 3 : shi + 1;
+        const int slo = shi - k + 1;
+        if (k == 3) cpass<3, false>(x, lg, slo, twl);
+        else if (k == 2) cpass<2, false>(x, lg, slo, twl);
+        else cpass<1, false>(x, lg, slo, twl);
+        shi = slo - 1;
+    }
+}
+__device__ __forceinline__ void dit1(double2 *x, int lg, const double2 *twl)
+{
+    for (int slo = 0; slo < lg;) {
+        const int k = lg - slo >= 3 ? 3 : lg - slo;
+        if (k == 3) cpass<3, true>(x, lg, slo, twl);
+        else if (k == 2) cpass<2, true>(x, lg, slo, twl);
+        else cpass<1, true>(x, lg, slo, twl);
+        slo += k;
+    }
+}
+
 // ------------------------------------------- split-precision (FP32 hi/lo)
 // The mixed-precision transforms hold every value as an unevaluated sum of
 // two FP32 numbers, hi + lo with |lo| <= ulp(hi)/2, and use error-free
@@ -580,6 +669,80 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     __syncthreads();
 }
 
+// The same correlation for N = 2^LGN in [16, 4096], using that the input and
+// the output are real: the input is packed into M = N/2 complex points,
+// z_n = x_{2n} + i x_{2n+1}, so one M-point transform gives the spectrum,
+//   X_k = ((Z_k + conj Z_{M-k}) - i W^k (Z_k - conj Z_{M-k})) / 2,  W = e^{-2 pi i/N},
+// and X_{M-k} from the same pair.  After the product with the kernel power
+// the output spectrum Y is packed back the same way (Y_{k+M} = conj Y_{M-k}),
+//   V_k = (Y_k + conj Y_{M-k}) + i conj(W^k) (Y_k - conj Y_{M-k}),
+// and one inverse M-point transform returns y_{2n} + i y_{2n+1}.  Bin k = 0
+// carries X_0 and X_M, both real; as in the full-length form, only the
+// Hermitian part of the product enters the real output, so the real parts of
+// Y_0 and Y_M are kept.
+__device__ __forceinline__ void tile_lds_real(const Mp &p, const JobArgs &j, double2 *lds, const double2 *twl)
+{
+    const int LGN = j.lgN, LGM = LGN - 1;
+    const int N = 1 << LGN, M = N / 2;
+    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const int tid = threadIdx.x;
+    const ll nin = j.n_in;
+    for (int n = tid; n < M; n += WG) {
+        const int t0 = 2 * n, t1 = 2 * n + 1;
+        const double a = t0 < nin ? tilt_in(j.src[t0], j.beta, t0, j.tc) : 0.0;
+        const double b = t1 < nin ? tilt_in(j.src[t1], j.beta, t1, j.tc) : 0.0;
+        lds[n] = make_double2(a, b);
+    }
+    __syncthreads();
+    dif1(lds, LGM, twl);
+    for (int k = tid; k <= M / 2; k += WG) {
+        if (k == 0) {
+            const double2 z = lds[0];
+            const double2 e = twl[2048];  // theta = pi
+            const double2 m0 = kernel_power(q, 1.0, 0.0, 0.0);
+            const double2 mm = kernel_power(q, e.x, -e.y, twl[1024].y);
+            const double y0 = 2.0 * (z.x + z.y) * m0.x;
+            const double ym = 2.0 * (z.x - z.y) * mm.x;
+            lds[0] = make_double2(y0 + ym, y0 - ym);
+            continue;
+        }
+        const unsigned ia = bitrev((unsigned)k, LGM), ib = bitrev((unsigned)(M - k), LGM);
+        const double2 A = lds[ia], B = lds[ib];
+        const double2 wk = twl[k << (12 - LGN)];     // W^k
+        const double2 hh = twl[k << (11 - LGN)];     // e^{-i pi k / N}
+        const double2 m1 = kernel_power(q, wk.x, -wk.y, hh.y);   // theta_k
+        const double2 m2 = kernel_power(q, -wk.x, -wk.y, hh.x);  // pi - theta_k
+        const double2 S = make_double2(A.x + B.x, A.y - B.y);    // A + conj B
+        const double2 D = make_double2(A.x - B.x, A.y + B.y);    // A - conj B
+        const double2 P = cmul(wk, D);
+        const double2 Xk = make_double2(S.x + P.y, S.y - P.x);    // S - i P
+        const double2 Xm = make_double2(S.x - P.y, -S.y - P.x);   // conj S - i conj P
+        const double2 Yk = cmul(Xk, m1), Ym = cmul(Xm, m2);
+        const double2 S2 = make_double2(Yk.x + Ym.x, Yk.y - Ym.y);  // Yk + conj Ym
+        const double2 D2 = make_double2(Yk.x - Ym.x, Yk.y + Ym.y);  // Yk - conj Ym
+        const double2 Q = cmulc(D2, wk);                            // conj(W^k) D2
+        lds[ia] = make_double2(S2.x - Q.y, S2.y + Q.x);
+        if (ib != ia) lds[ib] = make_double2(S2.x + Q.y, Q.x - S2.y);
+    }
+    __syncthreads();
+    dit1(lds, LGM, twl);
+    const double sc = 0.5 / (double)N;
+    for (ll t = tid; t < j.n_out; t += WG) {
+        const ll m = j.out_off + t;
+        const double2 v = lds[m >> 1];
+        j.dst[t] = tilt_out(((m & 1) ? v.y : v.x) * sc, j.beta, m);
+    }
+    __syncthreads();
+}
+
+// One LDS correlation: the real-packed form for N >= 16, the full-length one below.
+__device__ __forceinline__ void tile_lds_any(const Mp &p, const JobArgs &j, double2 *lds,
+                                             const double2 *__restrict__ tw, const double2 *twl)
+{
+    if (j.lgN >= 4) tile_lds_real(p, j, lds, twl);
+    else tile_lds(p, j, lds, tw, twl);
+}
+
 __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2 *lds, const double2 *__restrict__ tw,
                                              const double2 *twl)
 {
@@ -616,7 +779,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     double2 *row = j.scr + (ll)p1 * N2;
     for (int t = tid; t < N2; t += WG) lds[t] = row[t];
     __syncthreads();
-    lds_dif(lds, lg2, 1, twl);
+    dif1(lds, LG_NLDS, twl);
     double sr, cr;
     sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
     const double2 r1 = make_double2(cr, -sr);
@@ -629,7 +792,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
     }
     __syncthreads();
-    lds_dit_inv(lds, lg2, 1, twl);
+    dit1(lds, LG_NLDS, twl);
     for (int t = tid; t < N2; t += WG) row[t] = lds[t];
     __syncthreads();
 }
@@ -866,7 +1029,7 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
         else if (ph == 1) tile_rows_ff(p, j, t, l4, twl, twf);
         else tile_col_inv_ff(j, t, l4, tw, twf);
     } else if (j.kind == K_LDS) {
-        tile_lds(p, j, lds, tw, twl);
+        tile_lds_any(p, j, lds, tw, twl);
     } else if (ph == 0) {
         tile_col_fwd(j, t, lds, tw, twl);
     } else if (ph == 1) {
@@ -880,9 +1043,8 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
 // Executed by the 64 lanes of wave 0.  Lane l holds one cell of the current
 // row; the neighbour a row step needs comes from the next lane by a DPP wave
 // shift, and the cell beyond the band (an exercise cell) rides in as the
-// shift's fill value.  Exercise values are carried per lane by one
-// multiplication per row (S u^{col-i} gains a factor u per row down) and
-// re-seeded with exp() every RESEED rows.
+// shift's fill value.  Exercise values are carried per lane by one update per
+// row and re-seeded with exp() every 64 rows.
 //
 // Boundary tracking uses the structure the paper proves: from one row to the
 // next the last continuation cell either stays or moves one cell towards the
@@ -892,7 +1054,6 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
 // the red cells are contiguous; the two can differ only where rounding makes a
 // near-tie cell flip.  Per-row boundaries are collected (one row per lane, 64
 // rows per store) only when the caller asks for them.
-#define RESEED 64
 
 __device__ __forceinline__ unsigned long long row_mask(int last_lane)  // lanes 0..last_lane
 {
@@ -964,90 +1125,134 @@ __device__ __forceinline__ int resolve_block(unsigned mlo, unsigned mhi, int nb,
     return bc;
 }
 
-// Binomial: rows i0-1 .. i0-h from row i0, whose red cells are [c0, b]
-// (b - c0 + 1 <= BAND); columns >= c0 only.  Writes the red cells of row i0-h
-// to dst, the boundary of each row to bnd (may be NULL); returns the last red
-// column of row i0-h.  *v0 receives the final value of column c0.
-__device__ __forceinline__ ll band_bin(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
+// One row step of a lattice band (TRI: trinomial).  Lane l holds column c0+l;
+// e is the lane's exercise value S u^{.} - K, advanced to the new row by
+// e <- u e + K(u-1); f1 (f2) is the exercise value of column c0+64 (c0+65) in
+// the row being read, the cells beyond the band that enter through the
+// shift's fill.  Returns whether the lane's new cell is red (continuation >=
+// exercise).
+template <bool TRI>
+__device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, double &f2, double u, double ku, double w0,
+                                         double w1, double w2)
+{
+    // only lane 63 reads the fills, and there the shifted value is the fill
+    // itself: the next fill is computed from the shifted register
+    const double g1 = dpp_dn1(g, f1);
+    f1 = fma(g1, u, ku);
+    double c;
+    if (TRI) {
+        const double g2 = dpp_dn1(g1, f2);
+        f2 = fma(g2, u, ku);
+        c = fma(w2, g2, fma(w1, g1, w0 * g));
+    } else {
+        c = fma(w1, g1, w0 * g);
+    }
+    e = fma(e, u, ku);
+    g = vmax_f64(c, e);
+    return c >= e;
+}
+
+// Rows i0-1 .. i0-h of a lattice (binomial: row i has columns 0..i, cell j
+// reads j and j+1; trinomial: columns 0..2i, cell j reads j, j+1, j+2) from
+// row i0, whose red cells are [c0, b] (b - c0 + 1 <= BAND); columns >= c0
+// only.  Writes the red cells of row i0-h to dst, the boundary of each row to
+// bnd (may be NULL); returns the last red column of row i0-h.  *v0 receives
+// the final value of column c0.
+//
+// Rows go in blocks of up to 64.  The fast form of a block keeps, per lane,
+// only the number of red rows and the last red row; the block is accepted if
+// these show the structure of Corollary 2.6 / Theorem 4.2 -- each lane red in
+// a prefix of the rows, the red cells of every row contiguous from c0, and the
+// boundary dropping by at most one cell per row -- and every row of the block
+// lies inside the lattice for all 64 lanes.  Then row r's boundary is c0 - 1
+// plus the number of lanes red for more than r rows.  Otherwise (a near-tie
+// cell, rows near the apex) the block is stepped again from its saved first
+// row with the same arithmetic, collecting each row's ballot, and resolved
+// with the previous-cell rule.
+template <bool TRI>
+__device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
                                        ll *bnd, double *v0)
 {
     // indices fit in 32 bits (T <= 2^21): scalar 32-bit bookkeeping
     const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
     const int l = threadIdx.x & 63;
     const int j = c0 + l;
-    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1;
+    const int cs = TRI ? 1 : 2;   // exercise exponent: S u^{cs j - i}
+    const int wr = TRI ? 2 : 1;   // last column of row i: wr i
+    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1, w2 = TRI ? p.w2 : 0.0;
     const double u = exp(a);
-    double g = (j <= b) ? src[j] : ((j <= i0) ? S * exp((double)(2 * j - i0) * a) - K : 0.0);
+    const double ku = K * (u - 1.0);
+    double g = (j <= b) ? src[j] : ((j <= wr * i0) ? S * exp((double)(cs * j - i0) * a) - K : 0.0);
     int bc = b;
     for (int k0 = 0; k0 < h; k0 += 64) {
         const int nb = (h - k0) < 64 ? (h - k0) : 64;
-        const int itop = i0 - k0;                             // row above the block
-        double x = S * exp((double)(2 * j - itop) * a);           // S u^{2j-i}, row itop
-        double xn = S * exp((double)(2 * (c0 + BAND) - itop) * a);  // column c0+64
-        unsigned mlo = 0, mhi = 0;
-#pragma unroll 4
-        for (int r = 0; r < nb; ++r) {
-            const double gn = dpp_dn1(g, xn - K);  // exercise cell beyond the band
-            x *= u;
-            xn *= u;
-            const double c = fma(w1, gn, w0 * g);
-            const double e = x - K;
-            g = vmax_f64(c, e);
-            // lanes beyond the row's last column (j > i) are outside the tree
-            const unsigned long long m = __ballot(c >= e) & row_mask(itop - 1 - r - c0);
-            mlo = writelane(mlo, (unsigned)m, r);
-            mhi = writelane(mhi, (unsigned)(m >> 32), r);
+        const int itop = i0 - k0;  // row above the block
+        const double e0 = S * exp((double)(cs * j - itop) * a) - K;
+        const double f10 = S * exp((double)(cs * (c0 + BAND) - itop) * a) - K;
+        const double f20 = TRI ? fma(f10, u, ku) : 0.0;
+        const int L0 = bc - c0;
+        bool done = false;
+        if (wr * (itop - nb) - c0 >= 63 && L0 >= 0 && L0 <= 63) {
+            double gg = g, e = e0, f1 = f10, f2 = f20;
+            int cnt = 0, lastr = -1;
+            if (nb == 64) {
+#pragma unroll
+                for (int r = 0; r < 64; ++r) {
+                    const bool red = lat_step<TRI>(gg, e, f1, f2, u, ku, w0, w1, w2);
+                    cnt += red ? 1 : 0;
+                    lastr = red ? r : lastr;
+                }
+            } else {
+                for (int r = 0; r < nb; ++r) {
+                    const bool red = lat_step<TRI>(gg, e, f1, f2, u, ku, w0, w1, w2);
+                    cnt += red ? 1 : 0;
+                    lastr = red ? r : lastr;
+                }
+            }
+            const int nxt = __shfl_down(cnt, 1, 64);
+            const bool prefix = (cnt == 0) || (lastr == cnt - 1);
+            const bool shape = (l > L0) ? (cnt == 0)
+                                        : (l == L0 || cnt > nxt || (cnt == nb && nxt == nb));
+            if (__ballot(!(prefix && shape)) == 0ull) {
+                g = gg;
+                bc = c0 - 1 + (int)__popcll(__ballot(cnt == nb));
+                if (bnd) {
+                    int q = c0 - 1;
+                    for (int m = 0; m <= L0; ++m) q += (__builtin_amdgcn_readlane(cnt, m) > l) ? 1 : 0;
+                    if (l < nb) bnd[itop - 1 - l] = q;
+                }
+                done = true;
+            }
         }
-        int q;
-        bc = resolve_block<false>(mlo, mhi, nb, bc, c0, 0, -1, &q, 0);
-        if (bnd && l < nb) bnd[itop - 1 - l] = q;
+        if (!done) {
+            double e = e0, f1 = f10, f2 = f20;
+            unsigned mlo = 0, mhi = 0;
+            for (int r = 0; r < nb; ++r) {
+                const bool red = lat_step<TRI>(g, e, f1, f2, u, ku, w0, w1, w2);
+                // lanes beyond the row's last column are outside the lattice
+                const unsigned long long m = __ballot(red) & row_mask(wr * (itop - 1 - r) - c0);
+                mlo = writelane(mlo, (unsigned)m, r);
+                mhi = writelane(mhi, (unsigned)(m >> 32), r);
+            }
+            int q;
+            bc = resolve_block<TRI>(mlo, mhi, nb, bc, c0, 0, -1, &q, 2 * itop);
+            if (bnd && l < nb) bnd[itop - 1 - l] = q;
+        }
     }
     if (j <= bc) dst[j] = g;
     if (v0 && l == 0) *v0 = g;
     return bc;
 }
 
-// Trinomial: as band_bin; row i has columns 0..2i and each cell reads j, j+1,
-// j+2.  Below an entirely red row the row shrinks by two cells, and the
-// boundary is the row's last red cell.
-__device__ __forceinline__ ll band_tri(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
-                                       ll *bnd, double *v0)
+__device__ __forceinline__ ll band_bin(Mp p, ll i0, ll c0, ll h, ll b, const double *src, double *dst, ll *bnd,
+                                       double *v0)
 {
-    const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
-    const int l = threadIdx.x & 63;
-    const int j = c0 + l;
-    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1, w2 = p.w2;
-    const double u = exp(a);
-    double g = (j <= b) ? src[j] : ((j <= 2 * i0) ? S * exp((double)(j - i0) * a) - K : 0.0);
-    int bc = b;
-    for (int k0 = 0; k0 < h; k0 += 64) {
-        const int nb = (h - k0) < 64 ? (h - k0) : 64;
-        const int itop = i0 - k0;
-        double x = S * exp((double)(j - itop) * a);           // S u^{j-i}, row itop
-        double x1 = S * exp((double)(c0 + BAND - itop) * a);  // column c0+64
-        double x2 = x1 * u;                                   // column c0+65
-        unsigned mlo = 0, mhi = 0;
-#pragma unroll 4
-        for (int r = 0; r < nb; ++r) {
-            const double g1 = dpp_dn1(g, x1 - K);   // lane 63: column c0+64
-            const double g2 = dpp_dn1(g1, x2 - K);  // lane 62: c0+64, lane 63: c0+65
-            x *= u;
-            x1 *= u;
-            x2 *= u;
-            const double c = fma(w2, g2, fma(w1, g1, w0 * g));
-            const double e = x - K;
-            g = vmax_f64(c, e);
-            const unsigned long long m = __ballot(c >= e) & row_mask(2 * (itop - 1 - r) - c0);
-            mlo = writelane(mlo, (unsigned)m, r);
-            mhi = writelane(mhi, (unsigned)(m >> 32), r);
-        }
-        int q;
-        bc = resolve_block<true>(mlo, mhi, nb, bc, c0, 0, -1, &q, 2 * itop);
-        if (bnd && l < nb) bnd[itop - 1 - l] = q;
-    }
-    if (j <= bc) dst[j] = g;
-    if (v0 && l == 0) *v0 = g;
-    return bc;
+    return band_lat<false>(p, i0, c0, h, b, src, dst, bnd, v0);
+}
+__device__ __forceinline__ ll band_tri(Mp p, ll i0, ll c0, ll h, ll b, const double *src, double *dst, ll *bnd,
+                                       double *v0)
+{
+    return band_lat<true>(p, i0, c0, h, b, src, dst, bnd, v0);
 }
 
 // BSM put: steps n0+1 .. n0+h from step n0, whose exercise cells are k <= f
@@ -1160,6 +1365,16 @@ struct Pool {
 __device__ __forceinline__ unsigned long long rmw_read(unsigned long long *p)
 {
     return __hip_atomic_fetch_or(p, 0ull, __ATOMIC_RELAXED, AGENT);
+}
+// A workgroup barrier orders global stores only within the workgroup.  Where
+// one lane then releases them to other workgroups (publishing a job,
+// counting a finished tile), every wave first waits until its own stores
+// have completed, so that the lane's agent-scope release covers the stores
+// of the whole workgroup.
+__device__ __forceinline__ void sync_stores()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
 }
 __device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ ll now_ticks() { return (ll)__builtin_amdgcn_s_memrealtime(); }
@@ -1366,6 +1581,7 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
         } else if (tid == 0) {
             set_abort(pl);
         }
+        sync_stores();
         if (tid == 0) complete_tile(pl, ji, ph, a.ntile, a.nph);
         busy += clk() - t0;
         ++tiles;
@@ -1470,7 +1686,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
         return 0;
     }
     const bool publish = cx.pl.n_wg > 1 && (direct ? cx.tn.pub_direct != 0 : lgN >= cx.tn.pub_min_lg);
-    if (publish) __syncthreads();  // the workgroup's writes of the input row precede the release below
+    if (publish) sync_stores();  // the workgroup's writes of the input row precede the release below
     if (threadIdx.x == 0) {
         if (direct) cx.st->n_direct += 1;
         else cx.st->n_fft += 1;
@@ -1547,7 +1763,10 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
         if ((msg & 15) == 2) {
             const ll tb = clk();
             run_tile<PREC>(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf);
-            if (mode == 1 && threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
+            if (mode == 1) {
+                sync_stores();
+                if (threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
+            }
             work += clk() - tb;
         }
     }

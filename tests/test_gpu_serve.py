@@ -34,6 +34,12 @@ def ctx():
     c.close()
 
 
+def torch_sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
 def drain(srv, n, timeout_s=60.0):
     got = {}
     t0 = time.time()
@@ -77,7 +83,13 @@ def test_serve_mix_equals_alone(ctx, oracle_mod, precision):
     srv.close()
     say("server stats", st)
     assert st["completed"] == len(opts) and st["batches"] >= 2
-    alone, _, _ = binding.price_batch(ctx, opts, precision=precision)  # same schedule per option
+    L = binding.launch_batch(ctx, opts, precision=precision)  # same schedule per option
+    torch_sync()
+    alone = L.price.cpu().numpy()
+    errs = binding.batch_errors(L, len(opts))
+    if (errs != 0).any() or not np.isfinite(alone).all():
+        say("batch of the whole mix: errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)))
+    assert (errs == 0).all(), errs
     refs = oracle_mod.price_many(opts)
     tol = (parity.REL_MIXED, parity.ABS_MIXED_K) if precision else (parity.REL_FP64, parity.ABS_FP64_K)
     lat = []
