@@ -41,6 +41,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("aop_solver.hip", "aop_internal.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "solve_kernel_binomial_T2p20_64opt_hbm_traffic.md")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_02317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per solve_kernel launch from the committed counter summary.
+
+    The summary lists `key: value` lines; its figure is used only for the
+    workload it was measured on and only while the kernel sources hash to the
+    value recorded with it (null otherwise: the counters describe other code).
+    """
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        line = line.strip().lstrip("-* ").strip()
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip().strip("`")] = v.strip().strip("`")
+    if kv.get("workload") != workload:
+        return None, "counters were taken on another workload"
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None, "kernel changed since the counters were taken"
+    try:
+        return float(kv["traffic_bytes_per_launch"]), "rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated"
+    except (KeyError, ValueError):
+        return None, "summary has no traffic figure"
+
+
 def golden_prices(model: int, log2T: int):
     path = os.path.join(ROOT, "tests", "golden",
                         "oracle_%s_c%d_t%d.json" % (GOLDEN_NAME[model], CONFIG_ID[model], log2T))
@@ -232,6 +271,9 @@ def main():
                     "within_fp64_tolerance": within,
                     "reference": "CPU oracle (FP64 plain induction), stored"}
     ok = bool(np.all(status == 0) and np.all(np.isfinite(prices)))
+    workload = "%s American %s, FFT nonlinear stencil, T=2^%d, %d seeded options" % (
+        args.option_type, "put" if model == 2 else "call", args.log2T, n)
+    traffic, traffic_src = measured_traffic(workload)
 
     line = {
         "metric": METRIC,
@@ -246,13 +288,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s American %s, FFT nonlinear stencil, T=2^%d, %d seeded options"
-                               % (args.option_type, "put" if model == 2 else "call", args.log2T, n),
+        "config": {"workload": workload,
                    "option_type": args.option_type, "T": 1 << args.log2T, "options": n,
                    "seed": [CONFIG_ID[model], args.log2T], "precision": "fp64", "gpus": 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "solve_kernel",
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_s * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
+                     "kernel": "solve_kernel", "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_s * 1e3},
         "band_fp64": {"achieved": band_flops / avg_s / 1e12, "peak": FP64_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": band_flops / avg_s / 1e12 / FP64_VEC_PEAK_TFLOPS, "band_rows_per_launch": band_rows},
         "work": {f: int(st[:, i].sum()) for f, i in F.items()

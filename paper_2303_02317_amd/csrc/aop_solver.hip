@@ -221,95 +221,6 @@ __device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl)
     }
 }
 
-// Single transforms of 2^lg <= 2048 points in the same pass structure (radix
-// 8 from the top for the forward transform, from the bottom for the
-// inverse), without the batch bookkeeping of lds_pass: a radix-2^K pass over
-// stages slo+K-1 .. slo reads the K twiddles W_{2^{s+1}}^j of its group from
-// the table; the butterflies' remaining factors are powers of W_8, applied as
-// constants.
-__device__ __forceinline__ double2 rot_w8(double2 d, int e, bool cj)  // d * W_8^e (or conj), e < 4
-{
-    constexpr double R = 0.70710678118654752440;
-    if (e == 0) return d;
-    if (!cj) {
-        if (e == 2) return make_double2(d.y, -d.x);
-        if (e == 1) return make_double2((d.x + d.y) * R, (d.y - d.x) * R);
-        return make_double2((d.y - d.x) * R, -(d.x + d.y) * R);
-    }
-    if (e == 2) return make_double2(-d.y, d.x);
-    if (e == 1) return make_double2((d.x - d.y) * R, (d.x + d.y) * R);
-    return make_double2(-(d.x + d.y) * R, (d.x - d.y) * R);
-}
-
-template <int K, bool INV>
-__device__ __forceinline__ void cpass(double2 *x, int lg, int slo, const double2 *twl)
-{
-    constexpr int G = 1 << K;
-    const int per = (1 << lg) >> K;
-    const int jm = (1 << slo) - 1;
-    for (int gi = threadIdx.x; gi < per; gi += WG) {
-        const int j = gi & jm;
-        const int base = ((gi >> slo) << (slo + K)) + j;
-        double2 v[G], w[K];
-#pragma unroll
-        for (int q = 0; q < G; ++q) v[q] = x[base + (q << slo)];
-#pragma unroll
-        for (int t = 0; t < K; ++t) w[t] = twl[j << (11 - (slo + t))];
-        if (!INV) {
-#pragma unroll
-            for (int t = K - 1; t >= 0; --t) {
-#pragma unroll
-                for (int q = 0; q < G; ++q) {
-                    if (q & (1 << t)) continue;
-                    const double2 u = v[q], z = v[q + (1 << t)];
-                    v[q] = make_double2(u.x + z.x, u.y + z.y);
-                    const double2 d = rot_w8(make_double2(u.x - z.x, u.y - z.y), (q & ((1 << t) - 1)) << (2 - t), false);
-                    v[q + (1 << t)] = cmul(d, w[t]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < K; ++t) {
-#pragma unroll
-                for (int q = 0; q < G; ++q) {
-                    if (q & (1 << t)) continue;
-                    const double2 u = v[q];
-                    const double2 z = rot_w8(cmulc(v[q + (1 << t)], w[t]), (q & ((1 << t) - 1)) << (2 - t), true);
-                    v[q] = make_double2(u.x + z.x, u.y + z.y);
-                    v[q + (1 << t)] = make_double2(u.x - z.x, u.y - z.y);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < G; ++q) x[base + (q << slo)] = v[q];
-    }
-    __syncthreads();
-}
-
-// Forward (natural order in, bit-reversed out) and unnormalised inverse
-// (bit-reversed in, natural out) transforms of 2^lg points.
-__device__ __forceinline__ void dif1(double2 *x, int lg, const double2 *twl)
-{
-    for (int shi = lg - 1; shi >= 0;) {
-        const int k = shi + 1 >= 3 ? 3 : shi + 1;
-        const int slo = shi - k + 1;
-        if (k == 3) cpass<3, false>(x, lg, slo, twl);
-        else if (k == 2) cpass<2, false>(x, lg, slo, twl);
-        else cpass<1, false>(x, lg, slo, twl);
-        shi = slo - 1;
-    }
-}
-__device__ __forceinline__ void dit1(double2 *x, int lg, const double2 *twl)
-{
-    for (int slo = 0; slo < lg;) {
-        const int k = lg - slo >= 3 ? 3 : lg - slo;
-        if (k == 3) cpass<3, true>(x, lg, slo, twl);
-        else if (k == 2) cpass<2, true>(x, lg, slo, twl);
-        else cpass<1, true>(x, lg, slo, twl);
-        slo += k;
-    }
-}
-
 // ------------------------------------------- split-precision (FP32 hi/lo)
 // The mixed-precision transforms hold every value as an unevaluated sum of
 // two FP32 numbers, hi + lo with |lo| <= ulp(hi)/2, and use error-free
@@ -669,80 +580,6 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     __syncthreads();
 }
 
-// The same correlation for N = 2^LGN in [16, 4096], using that the input and
-// the output are real: the input is packed into M = N/2 complex points,
-// z_n = x_{2n} + i x_{2n+1}, so one M-point transform gives the spectrum,
-//   X_k = ((Z_k + conj Z_{M-k}) - i W^k (Z_k - conj Z_{M-k})) / 2,  W = e^{-2 pi i/N},
-// and X_{M-k} from the same pair.  After the product with the kernel power
-// the output spectrum Y is packed back the same way (Y_{k+M} = conj Y_{M-k}),
-//   V_k = (Y_k + conj Y_{M-k}) + i conj(W^k) (Y_k - conj Y_{M-k}),
-// and one inverse M-point transform returns y_{2n} + i y_{2n+1}.  Bin k = 0
-// carries X_0 and X_M, both real; as in the full-length form, only the
-// Hermitian part of the product enters the real output, so the real parts of
-// Y_0 and Y_M are kept.
-__device__ __forceinline__ void tile_lds_real(const Mp &p, const JobArgs &j, double2 *lds, const double2 *twl)
-{
-    const int LGN = j.lgN, LGM = LGN - 1;
-    const int N = 1 << LGN, M = N / 2;
-    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
-    const int tid = threadIdx.x;
-    const ll nin = j.n_in;
-    for (int n = tid; n < M; n += WG) {
-        const int t0 = 2 * n, t1 = 2 * n + 1;
-        const double a = t0 < nin ? tilt_in(j.src[t0], j.beta, t0, j.tc) : 0.0;
-        const double b = t1 < nin ? tilt_in(j.src[t1], j.beta, t1, j.tc) : 0.0;
-        lds[n] = make_double2(a, b);
-    }
-    __syncthreads();
-    dif1(lds, LGM, twl);
-    for (int k = tid; k <= M / 2; k += WG) {
-        if (k == 0) {
-            const double2 z = lds[0];
-            const double2 e = twl[2048];  // theta = pi
-            const double2 m0 = kernel_power(q, 1.0, 0.0, 0.0);
-            const double2 mm = kernel_power(q, e.x, -e.y, twl[1024].y);
-            const double y0 = 2.0 * (z.x + z.y) * m0.x;
-            const double ym = 2.0 * (z.x - z.y) * mm.x;
-            lds[0] = make_double2(y0 + ym, y0 - ym);
-            continue;
-        }
-        const unsigned ia = bitrev((unsigned)k, LGM), ib = bitrev((unsigned)(M - k), LGM);
-        const double2 A = lds[ia], B = lds[ib];
-        const double2 wk = twl[k << (12 - LGN)];     // W^k
-        const double2 hh = twl[k << (11 - LGN)];     // e^{-i pi k / N}
-        const double2 m1 = kernel_power(q, wk.x, -wk.y, hh.y);   // theta_k
-        const double2 m2 = kernel_power(q, -wk.x, -wk.y, hh.x);  // pi - theta_k
-        const double2 S = make_double2(A.x + B.x, A.y - B.y);    // A + conj B
-        const double2 D = make_double2(A.x - B.x, A.y + B.y);    // A - conj B
-        const double2 P = cmul(wk, D);
-        const double2 Xk = make_double2(S.x + P.y, S.y - P.x);    // S - i P
-        const double2 Xm = make_double2(S.x - P.y, -S.y - P.x);   // conj S - i conj P
-        const double2 Yk = cmul(Xk, m1), Ym = cmul(Xm, m2);
-        const double2 S2 = make_double2(Yk.x + Ym.x, Yk.y - Ym.y);  // Yk + conj Ym
-        const double2 D2 = make_double2(Yk.x - Ym.x, Yk.y + Ym.y);  // Yk - conj Ym
-        const double2 Q = cmulc(D2, wk);                            // conj(W^k) D2
-        lds[ia] = make_double2(S2.x - Q.y, S2.y + Q.x);
-        if (ib != ia) lds[ib] = make_double2(S2.x + Q.y, Q.x - S2.y);
-    }
-    __syncthreads();
-    dit1(lds, LGM, twl);
-    const double sc = 0.5 / (double)N;
-    for (ll t = tid; t < j.n_out; t += WG) {
-        const ll m = j.out_off + t;
-        const double2 v = lds[m >> 1];
-        j.dst[t] = tilt_out(((m & 1) ? v.y : v.x) * sc, j.beta, m);
-    }
-    __syncthreads();
-}
-
-// One LDS correlation: the real-packed form for N >= 16, the full-length one below.
-__device__ __forceinline__ void tile_lds_any(const Mp &p, const JobArgs &j, double2 *lds,
-                                             const double2 *__restrict__ tw, const double2 *twl)
-{
-    if (j.lgN >= 4) tile_lds_real(p, j, lds, twl);
-    else tile_lds(p, j, lds, tw, twl);
-}
-
 __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2 *lds, const double2 *__restrict__ tw,
                                              const double2 *twl)
 {
@@ -779,7 +616,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     double2 *row = j.scr + (ll)p1 * N2;
     for (int t = tid; t < N2; t += WG) lds[t] = row[t];
     __syncthreads();
-    dif1(lds, LG_NLDS, twl);
+    lds_dif(lds, lg2, 1, twl);
     double sr, cr;
     sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
     const double2 r1 = make_double2(cr, -sr);
@@ -792,7 +629,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
     }
     __syncthreads();
-    dit1(lds, LG_NLDS, twl);
+    lds_dit_inv(lds, lg2, 1, twl);
     for (int t = tid; t < N2; t += WG) row[t] = lds[t];
     __syncthreads();
 }
@@ -1029,7 +866,7 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
         else if (ph == 1) tile_rows_ff(p, j, t, l4, twl, twf);
         else tile_col_inv_ff(j, t, l4, tw, twf);
     } else if (j.kind == K_LDS) {
-        tile_lds_any(p, j, lds, tw, twl);
+        tile_lds(p, j, lds, tw, twl);
     } else if (ph == 0) {
         tile_col_fwd(j, t, lds, tw, twl);
     } else if (ph == 1) {
