@@ -97,9 +97,9 @@ def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
     cores = min(len(os.sched_getaffinity(0)), 16)
     # Sample: the first options of the same seeded batch, at a T whose Theta(T^2)
     # oracle cost per option is a few seconds (the oracle's T^2/s rate does not
-    # depend on T); 2 options per thread.
+    # depend on T); 4 options per thread.
     sT = min(log2T, 17 if model == 0 else 16)
-    sample = inputs.batch(CONFIG_ID[model], sT, 2 * cores, model)
+    sample = inputs.batch(CONFIG_ID[model], sT, 4 * cores, model)
     oracle.build()
     t0 = time.perf_counter()
     oracle.price_many(sample, threads=cores)
@@ -119,7 +119,10 @@ def serve_bench(ctx, n_req: int, load: float = 0.7):
 
     opts = inputs.serving_mix(n_req)
     cells = np.array([float(o["T"]) ** 2 for o in opts])
-    cfg = dict(hbm_budget=48 << 30, max_inflight=4, max_batch=64)
+    from paper_2303_02317_amd import autotune
+
+    # per size class schedules from the committed autotuner table
+    cfg = dict(hbm_budget=48 << 30, max_inflight=4, max_batch=64, tunings=autotune.server_table())
 
     def collect(srv, n, got, t_end=None):
         while len(got) < n:
@@ -177,7 +180,9 @@ def serve_bench(ctx, n_req: int, load: float = 0.7):
                           "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
                           "queue_p50_ms": 1e3 * float(np.percentile(que, 50)),
                           "batches": st_open["batches"], "peak_hbm_bytes": st_open["peak_bytes"]},
-            "config": dict(cfg, precision="fp64"), "all_ok": ok, "same_prices_both_runs": same}
+            "config": dict({k: v for k, v in cfg.items() if k != "tunings"}, precision="fp64",
+                           tuned_classes=len(cfg["tunings"])),
+            "all_ok": ok, "same_prices_both_runs": same}
 
 
 def main():
@@ -225,6 +230,9 @@ def main():
     log("bench: %s, T=2^%d, %d options, steps=%d warmup=%d" % (args.option_type, args.log2T, n, args.steps,
                                                                args.warmup))
     ctx = binding.Context(0)
+    from paper_2303_02317_amd import autotune
+
+    autotune.apply(ctx, model, 1 << args.log2T, 0)  # the tuned schedule of this size class, if any
     stream = torch.cuda.current_stream()
     ws = torch.empty(binding.workspace_bytes(opts), dtype=torch.uint8, device="cuda")
     L = None

@@ -200,8 +200,8 @@ typedef struct {
     int32_t workgroups;     /* persistent grid (0 = one per compute unit, at most 512) */
     int32_t pub_min_lg;     /* FFT correlations of size >= 2^pub_min_lg are published (1..30) */
     int32_t pub_direct;     /* 1: publish direct-stepping correlations too; 0: run them inline */
-    int32_t direct_max_h;   /* correlations with h <= this (and n <= direct_max_n) step directly */
-    int32_t direct_max_n;   /* <= 1024 */
+    int32_t direct_max_h;   /* correlations with h <= this (<= 448, and n <= direct_max_n) step directly */
+    int32_t direct_max_n;   /* <= 2048 */
     int32_t helper_idle_us; /* a helper workgroup leaves after this long without work (>= 1) */
     int64_t timeout_ms;     /* a wait longer than this aborts the launch: its options price NaN (> 0) */
 } aop_tuning;

@@ -30,12 +30,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_gfx950.json")
 
 CANDIDATES = [
-    dict(pub_min_lg=12, direct_max_h=160, direct_max_n=1024),
-    dict(pub_min_lg=11, direct_max_h=160, direct_max_n=1024),
-    dict(pub_min_lg=13, direct_max_h=160, direct_max_n=1024),
-    dict(pub_min_lg=11, direct_max_h=64, direct_max_n=1024),
-    dict(pub_min_lg=12, direct_max_h=96, direct_max_n=512),
-    dict(pub_min_lg=11, direct_max_h=128, direct_max_n=1024),
+    dict(pub_min_lg=13, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=12, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=14, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=15, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=16, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=20, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=13, direct_max_h=448, direct_max_n=2048),
+    dict(pub_min_lg=14, direct_max_h=448, direct_max_n=2048),
+    dict(pub_min_lg=11, direct_max_h=320, direct_max_n=2048),
 ]
 
 #: Size classes timed by default: the benchmark workloads' (model, log2 T).

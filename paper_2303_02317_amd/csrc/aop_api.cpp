@@ -232,7 +232,7 @@ Tune make_tune(const aop_tuning &t, double tick_hz, int32_t workgroups)
 bool tuning_valid(const aop_tuning &u)
 {
     return u.workgroups >= 1 && u.workgroups <= MAX_WG && u.pub_min_lg >= 1 && u.pub_min_lg <= 30 &&
-           u.direct_max_h >= 0 && u.direct_max_n >= 0 && u.direct_max_n <= 1024 && u.helper_idle_us >= 1 &&
+           u.direct_max_h >= 0 && u.direct_max_h <= DIRECT_MAX_H && u.direct_max_n >= 0 && u.direct_max_n <= DIRECT_MAX_N && u.helper_idle_us >= 1 &&
            u.timeout_ms > 0 && u.timeout_ms <= 3600000;
 }
 
@@ -304,10 +304,10 @@ aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         ctx->tick_hz = 1e3 * (double)khz;
     ctx->tuning.workgroups = std::min(ncu, aop::MAX_WG);
-    ctx->tuning.pub_min_lg = 12;
+    ctx->tuning.pub_min_lg = 13;
     ctx->tuning.pub_direct = 0;
-    ctx->tuning.direct_max_h = 160;
-    ctx->tuning.direct_max_n = 1024;
+    ctx->tuning.direct_max_h = 320;
+    ctx->tuning.direct_max_n = 2048;
     ctx->tuning.helper_idle_us = 20000;
     ctx->tuning.timeout_ms = 30000;
     if (hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess ||

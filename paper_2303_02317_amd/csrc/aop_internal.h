@@ -83,6 +83,8 @@ struct Tune {
     int64_t idle_ticks;    // wall-clock ticks a helper waits for work before it leaves
 };
 
+constexpr int DIRECT_MAX_N = 2048;  // longest directly stepped correlation (in segments of <= 1024 cells)
+constexpr int DIRECT_MAX_H = 448;   // deepest directly stepped correlation (its halo leaves room in a segment)
 constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22
 constexpr int64_t TW_N = int64_t(1) << LG_TW;
 

@@ -844,6 +844,53 @@ __device__ __forceinline__ void direct_wave(Mp p, const double *__restrict__ src
     }
 }
 
+// Direct stepping of a correlation whose input may exceed one wave's 1024
+// cells: the output is cut into segments, each computed by direct_wave from
+// its own input window (the segment plus the h-step dependency halo: span*h
+// cells to the right for the lattices, h on each side for the centred BSM
+// stencil).  Every output cell sees exactly the arithmetic of the unsplit
+// computation.  Segments k = part, part + nparts, ... go to the caller.
+__device__ __forceinline__ void direct_one(const Mp &p, const double *src, ll n_in, ll h, ll out_off, ll n_out,
+                                           double *dst)
+{
+    if (n_in <= 128) direct_wave<2>(p, src, n_in, h, out_off, n_out, dst);
+    else if (n_in <= 256) direct_wave<4>(p, src, n_in, h, out_off, n_out, dst);
+    else if (n_in <= 512) direct_wave<8>(p, src, n_in, h, out_off, n_out, dst);
+    else direct_wave<16>(p, src, n_in, h, out_off, n_out, dst);
+}
+__device__ __forceinline__ int direct_nseg(const Mp &p, ll n_in, ll h, ll n_out)
+{
+    const ll halo = (p.model == BINOMIAL) ? h : 2 * h;
+    if (n_in <= 1024) return 1;
+    const ll per = 1024 - halo;  // outputs per segment
+    return (int)((n_out + per - 1) / per);
+}
+__device__ __forceinline__ void direct_part(const Mp &p, const double *src, ll n_in, ll h, ll out_off, ll n_out,
+                                            double *dst, int part, int nparts)
+{
+    const int nseg = direct_nseg(p, n_in, h, n_out);
+    if (nseg == 1) {
+        if (part == 0) direct_one(p, src, n_in, h, out_off, n_out, dst);
+        return;
+    }
+    const ll per = (n_out + nseg - 1) / nseg;
+    for (int k = part; k < nseg; k += nparts) {
+        const ll a = (ll)k * per;
+        const ll b = (a + per < n_out) ? a + per : n_out;
+        if (p.model == BSM) {
+            // outputs a..b-1 are cells out_off+a .. out_off+b-1 of the input
+            const ll lo = out_off + a - h, hi = out_off + b + h;  // window [lo, hi), lo >= 0
+            const ll nin = (hi < n_in ? hi : n_in) - lo;
+            direct_one(p, src + lo, nin, h, h, b - a, dst + a);
+        } else {
+            const ll span = (p.model == BINOMIAL) ? 1 : 2;
+            const ll hi = b + span * h;
+            const ll nin = (hi < n_in ? hi : n_in) - a;
+            direct_one(p, src + a, nin, h, 0, b - a, dst + a);
+        }
+    }
+}
+
 __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 
 // One tile of a job, executed by the whole workgroup (control flow uniform).
@@ -852,12 +899,7 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
                                          const double2 *__restrict__ tw, const double2 *twl, const float4 *twf)
 {
     if (j.kind == K_DIRECT) {
-        if (threadIdx.x < 64) {
-            if (j.n_in <= 128) direct_wave<2>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-            else if (j.n_in <= 256) direct_wave<4>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-            else if (j.n_in <= 512) direct_wave<8>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-            else direct_wave<16>(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-        }
+        direct_part(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst, threadIdx.x >> 6, WG / 64);
         __syncthreads();
     } else if (PREC) {
         float4 *l4 = (float4 *)lds;
@@ -1669,7 +1711,7 @@ __device__ __forceinline__ void wave_sync()
 __device__ __forceinline__ bool wave_sized(const Mp &d, const Tune &tn, ll nred, ll h)
 {
     const ll n = (d.model == BSM) ? 2 * h : nred;
-    return n <= tn.direct_max_n && n <= 1024 && h <= 2 * (ll)tn.direct_max_h;
+    return n <= tn.direct_max_n && n <= DIRECT_MAX_N && h <= 2 * (ll)tn.direct_max_h;
 }
 
 #define WGS __HIP_MEMORY_SCOPE_WORKGROUP
@@ -1677,10 +1719,7 @@ __device__ __forceinline__ bool wave_sized(const Mp &d, const Tune &tn, ll nred,
 // One direct-stepping correlation by the calling wave.
 __device__ __forceinline__ void run_direct(const Mp &d, const WJob &j)
 {
-    if (j.n_in <= 128) direct_wave<2>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-    else if (j.n_in <= 256) direct_wave<4>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-    else if (j.n_in <= 512) direct_wave<8>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
-    else direct_wave<16>(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst);
+    direct_part(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst, 0, 1);
 }
 
 // Claim the next unclaimed ticket (one wave; -1 if none).

@@ -165,3 +165,29 @@ def test_golden_full_size(ctx, fname):
             fails.append(("boundary", k, rows[~ok][:5]))
     say(fname, "max rel err", max(parity.price_errors(p[k], r["price"])[1] for k, r in enumerate(recs)))
     assert not fails, fails[:4]
+
+
+SCHEDULES = [
+    ("default", {}),
+    ("wide direct", dict(direct_max_h=320, direct_max_n=2048)),
+    ("no direct", dict(direct_max_h=0)),
+    ("publish all", dict(pub_min_lg=1, pub_direct=1, direct_max_h=320, direct_max_n=2048)),
+]
+
+
+@pytest.mark.parametrize("name,sched", SCHEDULES, ids=[s[0] for s in SCHEDULES])
+def test_schedules_agree_with_oracle(ctx, oracle_mod, name, sched):
+    # The launch schedule (which correlations step directly, in how many
+    # segments, on which workgroup) must not change any result beyond rounding.
+    base = ctx.tuning()
+    opts = []
+    for m in (0, 1, 2):
+        for T in (3000, 5000, 12000):
+            opts += inputs.batch(800 + m, T % 64, 2, m, T=T)
+    try:
+        ctx.set_tuning(**sched)
+        say("schedule", name, ctx.tuning())
+        p, st, b = run(ctx, opts)
+    finally:
+        ctx.set_tuning(**base)
+    check_against_oracle(oracle_mod, opts, p, st, b)
