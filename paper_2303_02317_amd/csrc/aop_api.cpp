@@ -134,7 +134,8 @@ void geometry(Desc &d)
 
 size_t option_bytes(const Desc &d)
 {
-    return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.scr_len);
+    return align_up(sizeof(double) * (size_t)(2 * d.row_len + d.arena_len)) + align_up(16 * (size_t)d.scr_len) +
+           align_up(16 * (size_t)aop::SPC_E * (size_t)aop::spc_entry(d.nfft));
 }
 
 // Descriptors for the plain stencil: two row buffers per option.

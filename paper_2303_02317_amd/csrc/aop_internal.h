@@ -83,6 +83,15 @@ struct Tune {
     int64_t idle_ticks;    // wall-clock ticks a helper waits for work before it leaves
 };
 
+// Spectrum cache of a driver: SPC_E kernel spectra of correlations of up to
+// 2^SPC_LG points (bins 0 .. N/2), after the option's FFT scratch.
+constexpr int SPC_LG = 12;
+constexpr int SPC_E = 32;
+constexpr int64_t spc_entry(int64_t nfft)  // complex elements per cache entry
+{
+    const int64_t n = nfft < (int64_t(1) << SPC_LG) ? nfft : (int64_t(1) << SPC_LG);
+    return (n / 2 + 1 + 15) / 16 * 16;
+}
 constexpr int DIRECT_MAX_N = 2048;  // longest directly stepped correlation (in segments of <= 1024 cells)
 constexpr int DIRECT_MAX_H = 448;   // deepest directly stepped correlation (its halo leaves room in a segment)
 constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22

@@ -554,7 +554,7 @@ __device__ __forceinline__ JobArgs uni_args(JobArgs a)
 }
 
 __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 *lds, const double2 *__restrict__ tw,
-                                         const double2 *twl)
+                                         const double2 *twl, const double2 *spec = nullptr)
 {
     const int lgN = j.lgN;
     const ll N = ll(1) << lgN;
@@ -567,9 +567,14 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     lds_dif(lds, lgN, 1, twl);
     // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
     for (ll f = tid; f <= N / 2; f += WG) {
-        double cs, sn, sh;
-        bin_trig_lds(twl, f, lgN, cs, sn, sh);
-        const double2 m = kernel_power(q, cs, sn, sh);
+        double2 m;
+        if (spec) {
+            m = spec[f];
+        } else {
+            double cs, sn, sh;
+            bin_trig_lds(twl, f, lgN, cs, sn, sh);
+            m = kernel_power(q, cs, sn, sh);
+        }
         const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
         lds[t1] = cmul(lds[t1], m);
         if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
@@ -605,7 +610,8 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
 }
 
 __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int tile, double2 *lds,
-                                          const double2 *__restrict__ tw, const double2 *twl)
+                                          const double2 *__restrict__ tw, const double2 *twl,
+                                          const double2 *spec = nullptr)
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N2 = ll(1) << lg2;
@@ -624,9 +630,17 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     const double2 r2 = make_double2(cr, -sr);
     for (int t = tid; t < N2; t += WG) {
         const int k2 = (int)bitrev(t, lg2);
-        double cs, sn, sh;
-        bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
-        lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
+        double2 m;
+        if (spec) {
+            // bin f = k1 + N1 k2; above N/2 the mirror's conjugate
+            const ll N = ll(1) << lgN, f = k1 + (ll(k2) << lg1);
+            m = f <= N / 2 ? spec[f] : make_double2(spec[N - f].x, -spec[N - f].y);
+        } else {
+            double cs, sn, sh;
+            bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
+            m = kernel_power(q, cs, sn, sh);
+        }
+        lds[t] = cmul(lds[t], m);
     }
     __syncthreads();
     lds_dit_inv(lds, lg2, 1, twl);
@@ -893,10 +907,34 @@ __device__ __forceinline__ void direct_part(const Mp &p, const double *src, ll n
 
 __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 
+// The kernel spectrum of an h-step correlation of N = 2^lgN <= 2^SPC_LG
+// points, bins f = 0 .. N/2 (the rest is its mirror's conjugate), into out.
+// Sub-trapezoids of one level share their heights, so a driver reuses these
+// arrays across its private correlations (the spectrum cache in Ctx).
+__device__ __forceinline__ void spec_fill(const Mp &p, ll h, int lgN, double2 *out, const double2 *twl)
+{
+    const Spec q = make_spec(p, h, 0.0, 0.0);
+    const ll N = ll(1) << lgN;
+    for (ll f = threadIdx.x; f <= N / 2; f += WG) {
+        double cs, sn, sh;
+        if (lgN <= LG_NLDS) {
+            bin_trig_lds(twl, f, lgN, cs, sn, sh);
+        } else {  // lgN = 12: theta = 2 pi f / 4096 from the table, sin(theta / 2) directly
+            const double2 e = twl[f];
+            cs = e.x;
+            sn = -e.y;
+            double c2;
+            sincospi((double)f / (double)N, &sh, &c2);
+        }
+        out[f] = kernel_power(q, cs, sn, sh);
+    }
+}
+
 // One tile of a job, executed by the whole workgroup (control flow uniform).
 template <int PREC>
 __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, int t, double2 *lds,
-                                         const double2 *__restrict__ tw, const double2 *twl, const float4 *twf)
+                                         const double2 *__restrict__ tw, const double2 *twl, const float4 *twf,
+                                         const double2 *spec = nullptr)
 {
     if (j.kind == K_DIRECT) {
         direct_part(p, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst, threadIdx.x >> 6, WG / 64);
@@ -908,11 +946,11 @@ __device__ __forceinline__ void run_tile(const Mp &p, const JobArgs &j, int ph, 
         else if (ph == 1) tile_rows_ff(p, j, t, l4, twl, twf);
         else tile_col_inv_ff(j, t, l4, tw, twf);
     } else if (j.kind == K_LDS) {
-        tile_lds(p, j, lds, tw, twl);
+        tile_lds(p, j, lds, tw, twl, spec);
     } else if (ph == 0) {
         tile_col_fwd(j, t, lds, tw, twl);
     } else if (ph == 1) {
-        tile_rows(p, j, t, lds, tw, twl);
+        tile_rows(p, j, t, lds, tw, twl, spec);
     } else {
         tile_col_inv(j, t, lds, tw, twl);
     }
@@ -1355,6 +1393,8 @@ struct WQueue {
 struct Shared {
     WQueue wq;
     int msg, ji, opt, pad;
+    ll spk[SPC_E];  // spectrum cache keys (h << 8 | lgN), -1 empty
+    int spn, spx, spf, pad3;  // entries handed out; lookup result: entry, fill needed
     JobArgs args;          // arguments of the tile a helper claimed
     JobArgs jargs[JPW];    // arguments of each slot's pending job (driver)
     int pub[JPW];          // slot state: 0 idle, 1 published job pending, 2 private job pending
@@ -1494,6 +1534,8 @@ struct Ctx {
     ll arena_len;
     double2 *scr;
     ll scr_len;
+    double2 *spc;  // spectrum cache: SPC_E entries of spc_ent complex values
+    ll spc_ent;
     double2 *lds;
     const double2 *tw;
     const double2 *twl;
@@ -1587,6 +1629,32 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     return need;
 }
 
+// The cached kernel spectrum of an h-step correlation of 2^lgN points (all
+// threads call; filled on a miss, oldest entry replaced).
+__device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN)
+{
+    if (threadIdx.x == 0) {
+        const ll key = (h << 8) | lgN;
+        int x = -1;
+        for (int k = 0; k < SPC_E; ++k) x = (cx.sh->spk[k] == key) ? k : x;
+        cx.sh->spf = x < 0;
+        if (x < 0) {
+            x = cx.sh->spn % SPC_E;
+            cx.sh->spn += 1;
+            cx.sh->spk[x] = key;
+        }
+        cx.sh->spx = x;
+    }
+    __syncthreads();
+    const int x = __builtin_amdgcn_readfirstlane(cx.sh->spx);
+    double2 *e = cx.spc + (ll)x * cx.spc_ent;
+    if (__builtin_amdgcn_readfirstlane(cx.sh->spf)) {
+        spec_fill(cx.p, h, lgN, e, cx.twl);
+        sync_stores();
+    }
+    return e;
+}
+
 // Finish the pending job of `slot`: a private job's tiles are computed here
 // in order; for a published one the driver takes the tiles no other
 // workgroup has claimed and waits for the rest.
@@ -1599,6 +1667,10 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
     const int ji = blockIdx.x * JPW + slot;
     Job *jb = cx.pl.jobs + ji;
     const ll t0 = clk();
+    // a private FP64 transform takes its kernel spectrum from the cache
+    const bool cached = PREC == 0 && mode == 2 && a.kind != K_DIRECT && a.lgN <= SPC_LG &&
+                        __builtin_amdgcn_readfirstlane(a.beta == 0.0 ? 1 : 0);
+    const double2 *spec = cached ? spec_get(cx, a.h, a.lgN) : nullptr;
     const ll deadline = now_ticks() + cx.tn.timeout_ticks;
     ll work = 0;
     int nph = 0, nt = 0;  // private: next tile
@@ -1641,7 +1713,7 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
         }
         if ((msg & 15) == 2) {
             const ll tb = clk();
-            run_tile<PREC>(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf);
+            run_tile<PREC>(cx.p, a, (msg >> 4) & 15, msg >> 8, cx.lds, cx.tw, cx.twl, cx.twf, spec);
             if (mode == 1) {
                 sync_stores();
                 if (threadIdx.x == 0) complete_tile(cx.pl, ji, (msg >> 4) & 15, a.ntile, a.nph);
@@ -2414,6 +2486,8 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     cx.arena_len = d.arena_len;
     cx.scr = scr;
     cx.scr_len = d.scr_len;
+    cx.spc = scr + d.scr_len;
+    cx.spc_ent = spc_entry(d.nfft);
     cx.lds = lds;
     cx.tw = tw;
     cx.twl = twl;
@@ -2426,6 +2500,8 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     cx.sh = sh;
     cx.err_sh = err_sh;
     if (tid == 0) {
+        for (int k = 0; k < SPC_E; ++k) sh->spk[k] = -1;
+        sh->spn = 0;
         *err_sh = 0;
         *ret_sh = 0;
         *st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
