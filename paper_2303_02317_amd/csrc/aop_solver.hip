@@ -1883,6 +1883,19 @@ __device__ __forceinline__ bool wq_wait(const Mp &d, WQueue *q, int slot, int k,
     }
 }
 
+// A frame's scalar fields as wave-uniform values.
+__device__ __forceinline__ Frame uni_frame(Frame fr)
+{
+    fr.r0 = uni(fr.r0);
+    fr.c0 = uni(fr.c0);
+    fr.h = uni(fr.h);
+    fr.b = uni(fr.b);
+    fr.aoff = uni(fr.aoff);
+    fr.soff = uni(fr.soff);
+    fr.stage = __builtin_amdgcn_readfirstlane(fr.stage);
+    return fr;
+}
+
 // Wave-local solve of a small trapezoid (see wave_sized): wave 0 alone walks
 // the frame stages of solve_trapezoid -- first correlation, first
 // sub-trapezoid, second correlation, second sub-trapezoid -- stepping each
@@ -1896,20 +1909,13 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     const int span = (d.model == BINOMIAL) ? 1 : 2;
     const ll timeout = cx.tn.timeout_ticks;
     if (cap > WQ) cap = WQ;  // one outstanding correlation per frame fits the queue
-    if (l == 0) wstk[0] = root;
-    wave_sync();
+    // The frame being worked on (depth sp) lives in registers; the stack
+    // holds its ancestors, each stored when its child was entered.
     int sp = 0, tail = 0;
     ll rv = 0;
     int e = DEV_OK;
-    while (sp >= 0) {
-        Frame fr = wstk[sp];
-        fr.r0 = uni(fr.r0);
-        fr.c0 = uni(fr.c0);
-        fr.h = uni(fr.h);
-        fr.b = uni(fr.b);
-        fr.aoff = uni(fr.aoff);
-        fr.soff = uni(fr.soff);
-        fr.stage = __builtin_amdgcn_readfirstlane(fr.stage);
+    Frame fr = uni_frame(root);
+    for (;;) {
         // the frame's pending correlation (job index + 1 in soff) must be done
         // before its next stage reads its output
         if (fr.soff > 0) {
@@ -2045,24 +2051,24 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             }
         }
         if (pop) {
+            if (sp == 0) break;
             --sp;
+            fr = uni_frame(wstk[sp]);
         } else if (sp + 1 >= cap) {
             e = DEV_STACK;
             break;
         } else {
-            if (l == 0) {
-                wstk[sp] = fr;
-                wstk[sp + 1] = child;
-            }
+            if (l == 0) wstk[sp] = fr;  // read back by this wave only, after the child's subtree
             ++sp;
+            fr = child;
         }
-        wave_sync();
     }
     if (e != DEV_OK && e != DEV_TIMEOUT) {
-        // finish the outstanding jobs of the frames still on the stack
-        for (int k = sp; k >= 0; --k) {
+        // finish the outstanding jobs of this frame and of its ancestors
+        bool ok = fr.soff <= 0 || wq_wait(d, q, sp, (int)fr.soff - 1, timeout, cx.st);
+        for (int k = sp - 1; ok && k >= 0; --k) {
             const ll so = uni(wstk[k].soff);
-            if (so > 0 && !wq_wait(d, q, k, (int)so - 1, timeout, cx.st)) break;
+            if (so > 0) ok = wq_wait(d, q, k, (int)so - 1, timeout, cx.st);
         }
     }
     if (e != DEV_OK && l == 0 && *cx.err_sh == 0) *cx.err_sh = e;

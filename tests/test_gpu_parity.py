@@ -184,10 +184,20 @@ def test_schedules_agree_with_oracle(ctx, oracle_mod, name, sched):
     for m in (0, 1, 2):
         for T in (3000, 5000, 12000):
             opts += inputs.batch(800 + m, T % 64, 2, m, T=T)
+    import torch
+
+    from paper_2303_02317_amd import binding
+
     try:
         ctx.set_tuning(**sched)
         say("schedule", name, ctx.tuning())
-        p, st, b = run(ctx, opts)
+        L = binding.launch_batch(ctx, opts, boundary=True)
+        torch.cuda.synchronize()
     finally:
         ctx.set_tuning(**base)
+    p, st, b = L.price.cpu().numpy(), L.status.copy(), L.boundary.cpu().numpy()
+    errs = binding.batch_errors(L, len(opts))
+    if (errs != 0).any():
+        say("device errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)))
+    assert (errs == 0).all(), errs
     check_against_oracle(oracle_mod, opts, p, st, b)
