@@ -203,6 +203,9 @@ typedef struct {
     int32_t direct_max_h;   /* correlations with h <= this (<= 448, and n <= direct_max_n) step directly */
     int32_t direct_max_n;   /* <= 2048 */
     int32_t helper_idle_us; /* a helper workgroup leaves after this long without work (>= 1) */
+    int32_t late_pub_min_lg; /* once late_after_pct % of the launch's options are done, the drivers
+                                still running publish FFT correlations of size >= 2^this (0 = never) */
+    int32_t late_after_pct;  /* 0..100 */
     int64_t timeout_ms;     /* a wait longer than this aborts the launch: its options price NaN (> 0) */
 } aop_tuning;
 aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out);

@@ -38,7 +38,8 @@ POOL_FIELDS = ["workgroups", "helper_tiles", "helper_busy", "helper_idle", "opti
 class AopTuning(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int32), ("pub_min_lg", ctypes.c_int32), ("pub_direct", ctypes.c_int32),
                 ("direct_max_h", ctypes.c_int32), ("direct_max_n", ctypes.c_int32),
-                ("helper_idle_us", ctypes.c_int32), ("timeout_ms", ctypes.c_int64)]
+                ("helper_idle_us", ctypes.c_int32), ("late_pub_min_lg", ctypes.c_int32),
+                ("late_after_pct", ctypes.c_int32), ("timeout_ms", ctypes.c_int64)]
 
 
 class AopError(RuntimeError):

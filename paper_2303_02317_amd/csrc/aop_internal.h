@@ -79,6 +79,8 @@ struct Tune {
     int32_t direct_max_h;  // longest kernel evaluated by direct stepping
     int32_t direct_max_n;  // longest segment evaluated by direct stepping (<= 1024)
     int32_t prec;          // precision of the batch (every descriptor's): 0 FP64, 1 split-FP32 FFT
+    int32_t late_pub_lg;   // publication threshold once late_after options are done (0: never)
+    int32_t late_after;    // options done (set per launch from the percentage)
     int64_t timeout_ticks; // wall-clock ticks a wait may take before the launch aborts
     int64_t idle_ticks;    // wall-clock ticks a helper waits for work before it leaves
 };

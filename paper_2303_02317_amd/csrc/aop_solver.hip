@@ -1394,6 +1394,7 @@ struct Shared {
     WQueue wq;
     int msg, ji, opt, pad;
     ll spk[SPC_E];  // spectrum cache keys (h << 8 | lgN), -1 empty
+    int late, pad4[3];  // most of the launch's options are done: publish more (Tune::late_pub_lg)
     int spn, spx, spf, pad3;  // entries handed out; lookup result: entry, fill needed
     JobArgs args;          // arguments of the tile a helper claimed
     JobArgs jargs[JPW];    // arguments of each slot's pending job (driver)
@@ -1606,7 +1607,10 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
         set_err(cx, DEV_ARENA);
         return 0;
     }
-    const bool publish = cx.pl.n_wg > 1 && (direct ? cx.tn.pub_direct != 0 : lgN >= cx.tn.pub_min_lg);
+    // late in the launch most workgroups are idle helpers and fences are
+    // cheap: the drivers still running publish smaller correlations
+    const int thr = (cx.tn.late_pub_lg > 0 && cx.sh->late) ? cx.tn.late_pub_lg : cx.tn.pub_min_lg;
+    const bool publish = cx.pl.n_wg > 1 && (direct ? cx.tn.pub_direct != 0 : lgN >= thr);
     if (publish) sync_stores();  // the workgroup's writes of the input row precede the release below
     if (threadIdx.x == 0) {
         if (direct) cx.st->n_direct += 1;
@@ -2094,9 +2098,13 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
         *sp_sh = 0;
     }
     __syncthreads();
+    int iter = 0;
     for (;;) {
         const int s = *sp_sh;
         if (s < 0 || *cx.err_sh) break;
+        if (tid == 0 && cx.tn.late_pub_lg > 0 && !cx.sh->late && (++iter & 15) == 0 &&
+            (int)(rmw_read((unsigned long long *)&cx.pl.hdr->status) & 0xffffffffull) >= cx.tn.late_after)
+            cx.sh->late = 1;
         Frame fr = stk[s];
         fr.r0 = uni(fr.r0);
         fr.c0 = uni(fr.c0);
@@ -2508,6 +2516,7 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     if (tid == 0) {
         for (int k = 0; k < SPC_E; ++k) sh->spk[k] = -1;
         sh->spn = 0;
+        sh->late = 0;
         *err_sh = 0;
         *ret_sh = 0;
         *st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -2635,9 +2644,11 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
                        pl.hdr, pl.summary, pl.bits, n_wg);
     auto kern = tune.prec ? solve_kernel<1> : solve_kernel<0>;
     if (!d_err) d_err = (int32_t *)(d_ws + err_offset(n));
+    Tune tn = tune;
+    tn.late_after = (int32_t)(((int64_t)tune.late_after * n + 99) / 100);  // percentage -> options
     hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(WG), 0, (hipStream_t)stream, d_desc, (ll)n, d_ws,
                        (const double2 *)d_tw, d_price, (ll *)d_bnd, (ll)bnd_stride, d_err,
-                       (Stats *)(d_ws + stats_offset(n)), pl, tune);
+                       (Stats *)(d_ws + stats_offset(n)), pl, tn);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
