@@ -107,8 +107,8 @@ def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
     cells = sum(float(o["T"]) ** 2 for o in sample)
     return {"value": cells / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
             "seconds": round(dt, 3),
-            "sample": "first %d options of the same seeded batch (config id %d) at T=2^%d, one option per "
-                      "thread, plain FP64 backward induction" % (len(sample), CONFIG_ID[model], sT)}
+            "sample": "first %d options of the same seeded batch (config id %d) at T=2^%d on %d host threads "
+                      "(4 options each), plain FP64 backward induction" % (len(sample), CONFIG_ID[model], sT, cores)}
 
 
 def serve_bench(ctx, n_req: int, load: float = 0.7):
