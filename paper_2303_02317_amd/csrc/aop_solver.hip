@@ -1172,6 +1172,22 @@ __device__ __forceinline__ ll band_tri(Mp p, ll i0, ll c0, ll h, ll b, const dou
     return band_lat<true>(p, i0, c0, h, b, src, dst, bnd, v0);
 }
 
+// One step of the BSM band: the lane's cell moves one to the left; the new
+// cell k needs old cells k-1, k, k+1 = old lanes l-2, l-1, l, and lane 0
+// takes exercise values for the cells left of the band.  Returns whether the
+// new cell is continuation (not exercise).
+__device__ __forceinline__ bool bsm_step(double &v, double &x, double ud, double w0, double w1, double w2)
+{
+    x *= ud;                   // e^{s_k} of the lane's new cell
+    const double xm = x * ud;  // e^{s_{k-1}}
+    const double g = 1.0 - x;
+    const double vm1 = dpp_up1(v, g);
+    const double vm2 = dpp_up1(vm1, 1.0 - xm);
+    const double cont = fma(w2, v, fma(w1, vm1, w0 * vm2));
+    v = vmax_f64(cont, g);
+    return !(g > cont);
+}
+
 // BSM put: steps n0+1 .. n0+h from step n0, whose exercise cells are k <= f
 // and whose continuation cells [f+1, R0] are read from src (absolute k).  The
 // band's right edge starts at R0 and moves left one cell per step (the
@@ -1196,32 +1212,68 @@ __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const
     int fc = f;
     for (int t0 = 0; t0 < h; t0 += 64) {
         const int nb = (h - t0) < 64 ? (h - t0) : 64;
-        const int base0 = base;                      // band base before the block
-        double x = exp(s0 + (double)(base0 + l) * ds);  // e^{s_k} of the lane's cell before the block
-        unsigned mlo = 0, mhi = 0;
-#pragma unroll 4
-        for (int r = 0; r < nb; ++r) {
-            x *= ud;                   // the lane's new cell is one to the left
-            const double xm = x * ud;  // e^{s_{k-1}}
-            // new cell k needs old cells k-1, k, k+1 = old lanes l-2, l-1, l;
-            // lane 0 takes exercise values for the cells left of the band.
-            const double vm1 = dpp_up1(v, 1.0 - x);
-            const double vm2 = dpp_up1(vm1, 1.0 - xm);
-            const double cont = fma(w2, v, fma(w1, vm1, w0 * vm2));
-            const double g = 1.0 - x;
-            v = vmax_f64(cont, g);
-            const unsigned long long m = __ballot(g > cont);
-            mlo = writelane(mlo, (unsigned)m, r);
-            mhi = writelane(mhi, (unsigned)(m >> 32), r);
+        const int base0 = base;                           // band base before the block
+        const double x0 = exp(s0 + (double)(base0 + l) * ds);  // e^{s_k} of the lane's cell before the block
+        // Fast form (as band_lat): per lane the number of continuation rows and
+        // the last one.  Row r of the block has lane 0 at cell base0 - 1 - r, so
+        // the exercise cells (lanes 0 .. G_r - 1) grow by 0 or 1 lanes per row
+        // (Theorem 4.2: the boundary stays or moves one cell left).
+        bool done = false;
+        {
+            double vv = v, x = x0;
+            int cnt = 0, lastr = -1;
+            if (nb == 64) {
+#pragma unroll
+                for (int r = 0; r < 64; ++r) {
+                    const bool red = bsm_step(vv, x, ud, w0, w1, w2);
+                    cnt += red ? 1 : 0;
+                    lastr = red ? r : lastr;
+                }
+            } else {
+                for (int r = 0; r < nb; ++r) {
+                    const bool red = bsm_step(vv, x, ud, w0, w1, w2);
+                    cnt += red ? 1 : 0;
+                    lastr = red ? r : lastr;
+                }
+            }
+            const int nxt = __shfl_down(cnt, 1, 64);
+            const bool prefix = (cnt == 0) || (lastr == cnt - 1);
+            const bool shape = (l == 63) || cnt < nxt || (cnt == nxt && (cnt == 0 || cnt == nb));
+            const int g0 = (int)__popcll(__ballot(cnt == 0));  // exercise lanes of the first row
+            const int gin = fc - base0 + 1;
+            if (__ballot(!(prefix && shape)) == 0ull && g0 >= 1 && (g0 == gin || g0 == gin + 1)) {
+                v = vv;
+                const int glast = 64 - (int)__popcll(__ballot(cnt == nb));
+                fc = base0 - nb + glast - 1;
+                if (bnd) {
+                    int q = base0 - 1 - l - 1;
+                    for (int m = 0; m < 64; ++m) q += (__builtin_amdgcn_readlane(cnt, m) <= l) ? 1 : 0;
+                    if (l < nb) {
+                        const int n = n0 + t0 + 1 + l;
+                        bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
+                    }
+                }
+                done = true;
+            }
+        }
+        if (!done) {
+            double x = x0;
+            unsigned mlo = 0, mhi = 0;
+            for (int r = 0; r < nb; ++r) {
+                const bool red = bsm_step(v, x, ud, w0, w1, w2);
+                const unsigned long long m = __ballot(!red);  // exercise lanes
+                mlo = writelane(mlo, (unsigned)m, r);
+                mhi = writelane(mhi, (unsigned)(m >> 32), r);
+            }
+            int q;
+            // row r of the block has lane 0 at cell base0 - 1 - r
+            fc = resolve_block<false>(mlo, mhi, nb, fc, base0 - 1, -1, 0, &q, 0);
+            if (bnd && l < nb) {
+                const int n = n0 + t0 + 1 + l;
+                bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
+            }
         }
         base -= nb;
-        int q;
-        // row r of the block has lane 0 at cell base0 - 1 - r
-        fc = resolve_block<false>(mlo, mhi, nb, fc, base0 - 1, -1, 0, &q, 0);
-        if (bnd && l < nb) {
-            const int n = n0 + t0 + 1 + l;
-            bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
-        }
     }
     k = base + l;
     if (k > fc && k <= R0 - h) dst[k] = v;
