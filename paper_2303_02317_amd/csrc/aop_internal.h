@@ -62,7 +62,8 @@ constexpr int64_t JOB_BYTES = 128;
 constexpr int64_t POOL_SUMMARY = 128;                 // byte offset of the summary bitmap (up to 1024 bits)
 constexpr int64_t POOL_BITS = 256;                    // byte offset of the per-workgroup slot words
 constexpr int64_t POOL_JOBS = POOL_BITS + 8 * MAX_WG; // byte offset of the job slots
-constexpr int64_t POOL_BYTES = POOL_JOBS + JOB_BYTES * JPW * MAX_WG;
+constexpr int64_t POOL_DRV = POOL_JOBS + JOB_BYTES * JPW * MAX_WG;  // int32 per option (first MAX_WG): its driver
+constexpr int64_t POOL_BYTES = POOL_DRV + 4 * MAX_WG;
 // Per-option device error codes (DevErr, int32) after the counters.
 inline int64_t err_offset(int64_t n)
 {

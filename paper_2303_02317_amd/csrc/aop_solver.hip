@@ -1325,6 +1325,7 @@ struct Pool {
     unsigned long long *summary;  // bit w: workgroup w has a flagged slot (maintained loosely)
     unsigned long long *bits;     // [n_wg]: bit s of word w = slot s of workgroup w has claimable tiles
     Job *jobs;                    // [n_wg * JPW]
+    int *drivers;                 // [MAX_WG]: workgroup driving option o (-1 not yet claimed)
     int n_wg;
 };
 
@@ -1493,9 +1494,21 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
     const ll t_start = clk();
     ll busy = 0, tiles = 0;
     unsigned rot = blockIdx.x * 37u;
+    // Home driver: the helpers share the drivers out evenly (helper w serves
+    // option w mod n first), so that every option keeps a few helpers of its
+    // own instead of whatever the scan finds; any job may still be claimed.
+    int home = -1, home_tries = 0;
+    const int n_home = (int)(n < MAX_WG ? n : MAX_WG);
     for (;;) {
         if (tid < 64) {
             int msg = 0, ji = -1;  // 0 nothing, 1 tile, 2 exit
+            if (home < 0 && home_tries < 64) {
+                ++home_tries;
+                int hd = -1;
+                if (l == 0) hd = __hip_atomic_fetch_add(pl.drivers + (int)(blockIdx.x % (unsigned)n_home), 0, __ATOMIC_RELAXED, AGENT);
+                hd = __builtin_amdgcn_readfirstlane(hd);
+                if (hd >= 0 && hd != (int)blockIdx.x && hd < pl.n_wg) home = hd;
+            }
             unsigned long long st = 0ull, sw = 0ull;
             if (l == 0) st = rmw_read((unsigned long long *)&pl.hdr->status);
             if (l < nsum) sw = rmw_read(pl.summary + l);
@@ -1504,7 +1517,21 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
             if ((ll)(st & 0xffffffffull) >= n || (st >> 32) || now_ticks() - last_work > idle_ticks) {
                 msg = 2;
             } else {
-                const unsigned long long m = __ballot(sw != 0ull);
+                if (home >= 0) {
+                    int ok = 0, ph = 0, t = 0, cj = -1;
+                    if (l == 0) {
+                        const unsigned long long bw = rmw_read(pl.bits + home);
+                        if (bw) {
+                            cj = home * JPW + (63 - (int)__clzll(bw));  // deepest slot first
+                            ok = claim_tile(pl, cj, &ph, &t);
+                        }
+                    }
+                    if (__builtin_amdgcn_readfirstlane(ok)) {
+                        msg = 1 | (__builtin_amdgcn_readfirstlane(ph) << 4) | (__builtin_amdgcn_readfirstlane(t) << 8);
+                        ji = __builtin_amdgcn_readfirstlane(cj);
+                    }
+                }
+                const unsigned long long m = msg ? 0ull : __ballot(sw != 0ull);
                 if (m) {
                     // a workgroup with claimable work: rotate over summary words and bits
                     const int r = (int)(rot & 63u);
@@ -2630,6 +2657,7 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
         const ll o = __builtin_amdgcn_readfirstlane(sh.opt);
         __syncthreads();
         if (o >= n) break;
+        if (tid == 0 && o < MAX_WG) __hip_atomic_exchange(pl.drivers + o, (int)blockIdx.x, __ATOMIC_RELAXED, AGENT);
         const Desc d = descs[o];
         if (d.model < 0) {  // rejected on the host: no work, price NaN
             if (tid == 0) {
@@ -2652,7 +2680,8 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
 // read-modify-writes, so they are cleared with atomic exchanges too: the
 // clearing must be visible to those atomics even where consecutive kernels of a
 // captured graph run without the cache maintenance separate launches get.
-__global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsigned long long *bits, int n_wg)
+__global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsigned long long *bits, int *drivers,
+                                 int n_wg)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long *h64 = (unsigned long long *)hdr;
@@ -2660,6 +2689,7 @@ __global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsi
     else if (t < 16) __hip_atomic_exchange(h64 + t, 0ull, __ATOMIC_RELAXED, AGENT);
     if (t < MAX_WG / 64) __hip_atomic_exchange(summary + t, 0ull, __ATOMIC_RELAXED, AGENT);
     if (t < n_wg) __hip_atomic_exchange(bits + t, 0ull, __ATOMIC_RELAXED, AGENT);
+    if (t < MAX_WG) __hip_atomic_exchange(drivers + t, -1, __ATOMIC_RELAXED, AGENT);
 }
 
 __global__ void twiddle_kernel(double2 *tw)
@@ -2691,9 +2721,10 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
     pl.summary = (unsigned long long *)(pool + POOL_SUMMARY);
     pl.bits = (unsigned long long *)(pool + POOL_BITS);
     pl.jobs = (Job *)(pool + POOL_JOBS);
+    pl.drivers = (int *)(pool + POOL_DRV);
     pl.n_wg = n_wg;
     hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((MAX_WG + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       pl.hdr, pl.summary, pl.bits, n_wg);
+                       pl.hdr, pl.summary, pl.bits, pl.drivers, n_wg);
     auto kern = tune.prec ? solve_kernel<1> : solve_kernel<0>;
     if (!d_err) d_err = (int32_t *)(d_ws + err_offset(n));
     Tune tn = tune;
