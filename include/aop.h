@@ -188,6 +188,12 @@ aop_status aop_batch_errors(const void *d_workspace, int64_t n, int32_t *h_err);
  * workgroups, [2] helper busy cycles, [3] helper idle cycles, [4] options
  * finished, [5] 1 if the launch aborted (a wait passed its deadline or a job was refused), [6..7] 0. */
 aop_status aop_pool_stats(const void *d_workspace, int64_t n, int64_t h_out[8]);
+/* Diagnostics of an aborted launch on this workspace (synchronous): h_out[0] the
+ * first cause (0 none, 1 a helper refused a job's arguments, 2 a driver's wait
+ * passed its deadline, 3 a wait while retiring jobs after an error passed its
+ * deadline), h_out[1..6] details of that event (job slot, phase and tile or
+ * control word, job kind and sizes, workgroup), h_out[7] 0. */
+aop_status aop_pool_abort_info(const void *d_workspace, int64_t n, int64_t h_out[8]);
 
 /*
  * Launch tuning of the FFT path (per context; changes no result, only speed).

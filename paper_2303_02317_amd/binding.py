@@ -25,7 +25,7 @@ BSM_NONE = np.iinfo(np.int64).min
 #: Every symbol include/aop.h declares.
 EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
-           "aop_status_str", "aop_version", "aop_pool_stats", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
+           "aop_status_str", "aop_version", "aop_pool_stats", "aop_pool_abort_info", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
            "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
            "aop_graph_create", "aop_graph_launch", "aop_graph_destroy", "aop_batch_errors"]
 
@@ -98,6 +98,7 @@ def load():
         "aop_status_str": (ctypes.c_char_p, [I32]),
         "aop_version": (ctypes.c_char_p, []),
         "aop_pool_stats": (I32, [P, I64, P]),
+        "aop_pool_abort_info": (I32, [P, I64, P]),
         "aop_ctx_get_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
         "aop_ctx_set_tuning": (I32, [P, ctypes.POINTER(AopTuning)]),
         "aop_server_create": (I32, [P, ctypes.POINTER(AopServerConfig), ctypes.POINTER(P)]),
@@ -288,6 +289,17 @@ def pool_stats(launch: "Launch", n: int) -> dict:
     _check(load().aop_pool_stats(ctypes.c_void_p(launch.workspace.data_ptr()), n,
                                  out.ctypes.data_as(ctypes.c_void_p)), "aop_pool_stats")
     return {f: int(out[i]) for i, f in enumerate(POOL_FIELDS)}
+
+
+ABORT_FIELDS = ["reason", "slot", "phase_tile_or_ctl", "kind_sizes", "desc_nin_or_kind", "nout_or_wg", "ctl_or_slot", "unused"]
+
+
+def pool_abort_info(launch: "Launch", n: int) -> dict:
+    """First cause of an aborted launch (aop_pool_abort_info): reason 0 none, 1 refused job, 2/3 deadline."""
+    out = np.zeros(8, dtype=np.int64)
+    _check(load().aop_pool_abort_info(ctypes.c_void_p(launch.workspace.data_ptr()), n,
+                                      out.ctypes.data_as(ctypes.c_void_p)), "aop_pool_abort_info")
+    return {f: int(out[i]) for i, f in enumerate(ABORT_FIELDS)}
 
 
 def price_one(ctx: Context, opt, precision: int = AOP_FP64, boundary: bool = False):

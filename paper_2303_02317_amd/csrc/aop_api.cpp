@@ -559,6 +559,16 @@ aop_status aop_pool_stats(const void *d_ws, int64_t n, int64_t *h_out)
     return AOP_OK;
 }
 
+aop_status aop_pool_abort_info(const void *d_ws, int64_t n, int64_t *h_out)
+{
+    if (!d_ws || !h_out || n < 0) return AOP_EINVAL;
+    aop::PoolHdr hdr;
+    if (hipMemcpy(&hdr, (const char *)d_ws + aop::pool_offset(n), sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+        return AOP_EDEVICE;
+    for (int k = 0; k < 8; ++k) h_out[k] = hdr.abort_info[k];
+    return AOP_OK;
+}
+
 aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out)
 {
     if (!ctx || !out) return AOP_EINVAL;

@@ -55,7 +55,8 @@ struct PoolHdr {
     uint32_t next_option, n_wg;
     uint64_t status;  // options finished (low 32 bits) | launch aborted (bit 32)
     int64_t helper_tiles, helper_busy, helper_idle;
-    int64_t reserved[11];
+    int64_t abort_info[8];  // first cause of an abort: reason (1 refused job, 2 wait deadline, 3 drain deadline), details
+    int64_t reserved[3];
 };
 static_assert(sizeof(PoolHdr) == 128, "pool header is 128 bytes");
 constexpr int64_t JOB_BYTES = 128;

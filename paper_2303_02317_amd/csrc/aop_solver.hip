@@ -1353,6 +1353,18 @@ __device__ __forceinline__ void set_abort(const Pool &pl)
 {
     __hip_atomic_fetch_or((unsigned long long *)&pl.hdr->status, 1ull << 32, __ATOMIC_RELAXED, AGENT);
 }
+// Abort the launch and, if this is the first cause, record it (aop_pool_abort_info).
+__device__ __forceinline__ void note_abort(const Pool &pl, ll reason, ll i1, ll i2, ll i3, ll i4, ll i5, ll i6)
+{
+    unsigned long long *w = (unsigned long long *)pl.hdr->abort_info;
+    unsigned long long expect = 0ull;
+    if (__hip_atomic_compare_exchange_strong(w, &expect, (unsigned long long)reason, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             AGENT)) {
+        const ll v[6] = {i1, i2, i3, i4, i5, i6};
+        for (int k = 0; k < 6; ++k) __hip_atomic_exchange(w + 1 + k, (unsigned long long)v[k], __ATOMIC_RELAXED, AGENT);
+    }
+    set_abort(pl);
+}
 
 // The summary bit of workgroup w may be stale in either direction; a helper
 // that finds it set over an empty word clears it, and whoever clears it
@@ -1410,13 +1422,17 @@ __device__ __forceinline__ void complete_tile(const Pool &pl, int ji, int ph, in
     }
 }
 
-// Copy a job's arguments into LDS (lanes 0..11 of wave 0, after the claim's acquire).
+// Copy a job's arguments into LDS (lanes 0..11 of wave 0, after the claim's
+// acquire).  A slot's arguments are rewritten for every job published in it,
+// so this workgroup's L2 may still hold the previous job's: like the control
+// words they are read with atomic read-modify-writes (and written with atomic
+// exchanges), which are performed at the device's coherence point.
 __device__ __forceinline__ void fetch_args(const Pool &pl, int ji, JobArgs *sh)
 {
     const int l = threadIdx.x;
     if (l < (int)(sizeof(JobArgs) / 8)) {
         unsigned long long *w = (unsigned long long *)&pl.jobs[ji].a;
-        ((unsigned long long *)sh)[l] = __hip_atomic_load(w + l, __ATOMIC_RELAXED, AGENT);
+        ((unsigned long long *)sh)[l] = rmw_read(w + l);
     }
 }
 
@@ -1578,7 +1594,9 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
             const Mp p = make_mp(descs[a.desc]);
             run_tile<PREC>(p, a, ph, tile, lds, tw, twl, twf);
         } else if (tid == 0) {
-            set_abort(pl);
+            note_abort(pl, 1, ji, ((ll)ph << 32) | tile,
+                       ((ll)a.kind << 48) | ((ll)a.nph << 40) | ((ll)a.lgN << 32) | (ll)(unsigned)a.ntile,
+                       ((ll)a.desc << 32) | (ll)(unsigned)a.n_in, a.n_out, (ll)rmw_read(&pl.jobs[ji].ctl));
         }
         sync_stores();
         if (tid == 0) complete_tile(pl, ji, ph, a.ntile, a.nph);
@@ -1699,7 +1717,9 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
         if (publish) {
             const int ji = blockIdx.x * JPW + slot;
             Job *jb = cx.pl.jobs + ji;
-            jb->a = a;
+            const unsigned long long *aw = (const unsigned long long *)&a;
+            for (int k = 0; k < (int)(sizeof(JobArgs) / 8); ++k)
+                __hip_atomic_exchange((unsigned long long *)&jb->a + k, aw[k], __ATOMIC_RELAXED, AGENT);
             for (int k = 0; k < 3; ++k) __hip_atomic_exchange(&jb->done[k], 0u, __ATOMIC_RELAXED, AGENT);
             const unsigned gen = cx.sh->gen[slot] + 1;
             cx.sh->gen[slot] = gen;
@@ -1776,8 +1796,11 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
                         m = 1;
                     } else if (p < 3 && ctl_claimed(c) < ctl_total(c) && claim_tile(cx.pl, ji, &ph, &t)) {
                         m = 2 | (ph << 4) | (t << 8);
-                    } else if (aborted(cx.pl) || now_ticks() > deadline) {
-                        set_abort(cx.pl);
+                    } else if (aborted(cx.pl)) {
+                        m = 3;
+                    } else if (now_ticks() > deadline) {
+                        note_abort(cx.pl, 2, ji, (ll)c, ((ll)a.nph << 32) | (ll)(unsigned)a.ntile,
+                                   ((ll)a.kind << 32) | (ll)(unsigned)a.lgN, blockIdx.x, slot);
                         m = 3;
                     } else {
                         __builtin_amdgcn_s_sleep(1);
@@ -1831,8 +1854,10 @@ __device__ __forceinline__ void drain(const Ctx &cx)
                     if (p == PH_DONE) break;
                     if (p < 3 && ctl_claimed(c) < ctl_total(c) && claim_tile(cx.pl, ji, &ph, &t)) {
                         complete_tile(cx.pl, ji, ph, a.ntile, a.nph);
-                    } else if (aborted(cx.pl) || now_ticks() > deadline) {
-                        set_abort(cx.pl);
+                    } else if (aborted(cx.pl)) {
+                        break;
+                    } else if (now_ticks() > deadline) {
+                        note_abort(cx.pl, 3, ji, (ll)c, ((ll)a.nph << 32) | (ll)(unsigned)a.ntile, 0, blockIdx.x, slot);
                         break;
                     } else {
                         __builtin_amdgcn_s_sleep(1);
@@ -1845,10 +1870,11 @@ __device__ __forceinline__ void drain(const Ctx &cx)
     __syncthreads();
 }
 
-// Read one double a pool job wrote (after conv_wait's acquire), as a vector load.
+// Read one double a pool job wrote (after conv_wait's acquire), with an
+// atomic read-modify-write like the pool's shared words.
 __device__ __forceinline__ double read_result(const double *p)
 {
-    unsigned long long v = __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, AGENT);
+    const unsigned long long v = rmw_read((unsigned long long *)p);
     return __longlong_as_double((long long)v);
 }
 
@@ -2676,12 +2702,17 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
 }
 
 // Clears the pool header, the summary bitmap and the slot words before a
-// launch.  The solve kernel reads these words only with atomic
-// read-modify-writes, so they are cleared with atomic exchanges too: the
-// clearing must be visible to those atomics even where consecutive kernels of a
-// captured graph run without the cache maintenance separate launches get.
+// launch, and sets every job slot's control word to "done" with zero counts.
+// A helper may see a slot's flag before the owner's store of the slot's new
+// control word (the flag is set after it, without ordering), and its claim
+// then lands on the previous value: within a launch that is a finished job,
+// on which a claim fails; before a slot's first job it must be one as well,
+// not whatever the workspace held.  The solve kernel reads these words only
+// with atomic read-modify-writes, so they are written with atomic exchanges:
+// the writes must be visible to those atomics even where consecutive kernels
+// of a captured graph run without the cache maintenance separate launches get.
 __global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsigned long long *bits, int *drivers,
-                                 int n_wg)
+                                 Job *jobs, int n_wg)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long *h64 = (unsigned long long *)hdr;
@@ -2690,6 +2721,11 @@ __global__ void pool_init_kernel(PoolHdr *hdr, unsigned long long *summary, unsi
     if (t < MAX_WG / 64) __hip_atomic_exchange(summary + t, 0ull, __ATOMIC_RELAXED, AGENT);
     if (t < n_wg) __hip_atomic_exchange(bits + t, 0ull, __ATOMIC_RELAXED, AGENT);
     if (t < MAX_WG) __hip_atomic_exchange(drivers + t, -1, __ATOMIC_RELAXED, AGENT);
+    if (t < n_wg * JPW) {
+        Job *jb = jobs + t;
+        __hip_atomic_exchange(&jb->ctl, mkctl(0, PH_DONE, 0, 0), __ATOMIC_RELAXED, AGENT);
+        for (int k = 0; k < 3; ++k) __hip_atomic_exchange(&jb->done[k], 0u, __ATOMIC_RELAXED, AGENT);
+    }
 }
 
 __global__ void twiddle_kernel(double2 *tw)
@@ -2723,8 +2759,9 @@ int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, do
     pl.jobs = (Job *)(pool + POOL_JOBS);
     pl.drivers = (int *)(pool + POOL_DRV);
     pl.n_wg = n_wg;
-    hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((MAX_WG + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       pl.hdr, pl.summary, pl.bits, pl.drivers, n_wg);
+    const int n_init = n_wg * JPW > MAX_WG ? n_wg * JPW : MAX_WG;  // threads: job slots, driver entries
+    hipLaunchKernelGGL(pool_init_kernel, dim3((unsigned)((n_init + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       pl.hdr, pl.summary, pl.bits, pl.drivers, pl.jobs, n_wg);
     auto kern = tune.prec ? solve_kernel<1> : solve_kernel<0>;
     if (!d_err) d_err = (int32_t *)(d_ws + err_offset(n));
     Tune tn = tune;

@@ -198,6 +198,6 @@ def test_schedules_agree_with_oracle(ctx, oracle_mod, name, sched):
     p, st, b = L.price.cpu().numpy(), L.status.copy(), L.boundary.cpu().numpy()
     errs = binding.batch_errors(L, len(opts))
     if (errs != 0).any():
-        say("device errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)))
+        say("device errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)), "abort", binding.pool_abort_info(L, len(opts)))
     assert (errs == 0).all(), errs
     check_against_oracle(oracle_mod, opts, p, st, b)

@@ -88,7 +88,7 @@ def test_serve_mix_equals_alone(ctx, oracle_mod, precision):
     alone = L.price.cpu().numpy()
     errs = binding.batch_errors(L, len(opts))
     if (errs != 0).any() or not np.isfinite(alone).all():
-        say("batch of the whole mix: errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)))
+        say("batch of the whole mix: errors", errs.tolist(), "pool", binding.pool_stats(L, len(opts)), "abort", binding.pool_abort_info(L, len(opts)))
     assert (errs == 0).all(), errs
     refs = oracle_mod.price_many(opts)
     tol = (parity.REL_MIXED, parity.ABS_MIXED_K) if precision else (parity.REL_FP64, parity.ABS_FP64_K)
