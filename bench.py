@@ -111,7 +111,7 @@ def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
                       "(4 options each), plain FP64 backward induction" % (len(sample), CONFIG_ID[model], sT, cores)}
 
 
-def serve_bench(ctx, n_req: int, load: float = 0.7):
+def serve_bench(ctx, n_req: int, load: float = 0.7, max_inflight: int = 4, max_batch: int = 64):
     """Serving mix: closed-loop capacity, then an open loop of Poisson arrivals at load x capacity."""
     import numpy as np
 
@@ -122,7 +122,7 @@ def serve_bench(ctx, n_req: int, load: float = 0.7):
     from paper_2303_02317_amd import autotune
 
     # per size class schedules from the committed autotuner table
-    cfg = dict(hbm_budget=48 << 30, max_inflight=4, max_batch=64, tunings=autotune.server_table())
+    cfg = dict(hbm_budget=48 << 30, max_inflight=max_inflight, max_batch=max_batch, tunings=autotune.server_table())
 
     def collect(srv, n, got, t_end=None):
         while len(got) < n:
