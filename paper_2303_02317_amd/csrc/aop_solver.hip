@@ -32,6 +32,8 @@ namespace aop {
 #define WG 256
 #define NLDS 2048  // complex doubles staged in LDS per FFT tile (32 KB)
 #define LG_NLDS 11
+#define NLDS64 4096  // FP64 transforms of up to this many points run whole in LDS (64 KB)
+#define LG_NLDS64 12
 #define MAXD 48    // recursion depth bound (log2 of 2^22 plus slack)
 #define BAND 64    // cells held by the band walker (one per lane)
 
@@ -447,13 +449,21 @@ __device__ __forceinline__ double2 twl_at(const double2 *twl, int t)  // any t i
     const double2 w = twl[t - 2048];  // e^{-i pi} e^{-2 pi i (t - 2048) / 4096}
     return make_double2(-w.x, -w.y);
 }
-// Bin f of a transform of 2^lgN <= 2048 points: theta = 2 pi f / N, f <= N / 2.
+// Largest transform (log2 of its points) that runs whole in LDS.
+__device__ __forceinline__ int lds_lg(int prec) { return prec ? LG_NLDS : LG_NLDS64; }
+
+// Bin f of a transform of 2^lgN <= 4096 points: theta = 2 pi f / N, f <= N / 2.
 __device__ __forceinline__ void bin_trig_lds(const double2 *twl, ll f, int lgN, double &cs, double &sn, double &sh)
 {
     const double2 e = twl[f << (12 - lgN)];
     cs = e.x;
     sn = -e.y;
-    sh = twl[f << (11 - lgN)].y;
+    if (lgN <= LG_NLDS) {
+        sh = twl[f << (11 - lgN)].y;
+    } else {  // 4096 points: theta / 2 is not on the table's grid
+        double c2;
+        sincospi((double)f / (double)(ll(1) << lgN), &sh, &c2);
+    }
 }
 // Bin k1 + N1 k2 of a four-step transform (N = N1 * 2048): r1 = e^{-2 pi i k1/N}
 // and r2 = e^{-i pi k1/N} are the tile's row factors, the rest comes from LDS.
@@ -553,6 +563,7 @@ __device__ __forceinline__ JobArgs uni_args(JobArgs a)
     return u;
 }
 
+// One whole transform in LDS (FP64, N <= 4096).
 __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 *lds, const double2 *__restrict__ tw,
                                          const double2 *twl, const double2 *spec = nullptr)
 {
@@ -561,23 +572,34 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     const double invN = 1.0 / (double)N;
     const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
     const int tid = threadIdx.x;
-    for (int t = tid; t < N; t += WG)
-        lds[t] = make_double2(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0);
+    // unrolled so that several global loads are in flight at once
+    if (j.beta == 0.0) {
+#pragma unroll 4
+        for (int t = tid; t < N; t += WG) lds[t] = make_double2(t < j.n_in ? j.src[t] : 0.0, 0.0);
+    } else {
+        for (int t = tid; t < N; t += WG)
+            lds[t] = make_double2(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0);
+    }
     __syncthreads();
     lds_dif(lds, lgN, 1, twl);
     // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
-    for (ll f = tid; f <= N / 2; f += WG) {
-        double2 m;
-        if (spec) {
-            m = spec[f];
-        } else {
+    if (spec) {
+#pragma unroll 4
+        for (int f = tid; f <= N / 2; f += WG) {
+            const double2 m = spec[f];
+            const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
+            lds[t1] = cmul(lds[t1], m);
+            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
+        }
+    } else {
+        for (int f = tid; f <= N / 2; f += WG) {
             double cs, sn, sh;
             bin_trig_lds(twl, f, lgN, cs, sn, sh);
-            m = kernel_power(q, cs, sn, sh);
+            const double2 m = kernel_power(q, cs, sn, sh);
+            const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
+            lds[t1] = cmul(lds[t1], m);
+            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
         }
-        const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
-        lds[t1] = cmul(lds[t1], m);
-        if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
     }
     __syncthreads();
     lds_dit_inv(lds, lgN, 1, twl);
@@ -590,18 +612,25 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
-    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int N1 = 1 << lg1, lgC = lg2 - lg1, C = 1 << lgC;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
+    // unrolled so that several global loads are in flight at once
+#pragma unroll 4
     for (int t = tid; t < NLDS; t += WG) {
-        const int c = t % C, n1 = t / C;
+        const int c = t & (C - 1), n1 = t >> lgC;
         const ll idx = (ll)n1 * N2 + n20 + c;
-        lds[c * N1 + n1] = make_double2(idx < j.n_in ? tilt_in(j.src[idx], j.beta, idx, j.tc) : 0.0, 0.0);
+        lds[c * N1 + n1] = make_double2(idx < j.n_in ? j.src[idx] : 0.0, 0.0);
     }
+    if (j.beta != 0.0)  // the same elements, in the same threads: no barrier needed in between
+        for (int t = tid; t < NLDS; t += WG) {
+            const int c = t & (C - 1), n1 = t >> lgC;
+            lds[c * N1 + n1].x = tilt_in(lds[c * N1 + n1].x, j.beta, (ll)n1 * N2 + n20 + c, j.tc);
+        }
     __syncthreads();
     lds_dif(lds, lg1, C, twl);
     for (int t = tid; t < NLDS; t += WG) {
-        const int c = t % C, p1 = t / C;
+        const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
         const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
         j.scr[(ll)p1 * N2 + n2] = cmul(lds[c * N1 + p1], w);
@@ -620,27 +649,30 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     const int p1 = tile;
     const ll k1 = bitrev(p1, lg1);
     double2 *row = j.scr + (ll)p1 * N2;
+#pragma unroll 4
     for (int t = tid; t < N2; t += WG) lds[t] = row[t];
     __syncthreads();
     lds_dif(lds, lg2, 1, twl);
-    double sr, cr;
-    sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
-    const double2 r1 = make_double2(cr, -sr);
-    sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
-    const double2 r2 = make_double2(cr, -sr);
-    for (int t = tid; t < N2; t += WG) {
-        const int k2 = (int)bitrev(t, lg2);
-        double2 m;
-        if (spec) {
-            // bin f = k1 + N1 k2; above N/2 the mirror's conjugate
-            const ll N = ll(1) << lgN, f = k1 + (ll(k2) << lg1);
-            m = f <= N / 2 ? spec[f] : make_double2(spec[N - f].x, -spec[N - f].y);
-        } else {
-            double cs, sn, sh;
-            bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
-            m = kernel_power(q, cs, sn, sh);
+    if (spec) {
+        // bin f = k1 + N1 k2; above N/2 the mirror's conjugate
+        const ll N = ll(1) << lgN;
+#pragma unroll 4
+        for (int t = tid; t < N2; t += WG) {
+            const ll f = k1 + (ll(bitrev(t, lg2)) << lg1);
+            const double2 e = spec[f <= N / 2 ? f : N - f];
+            lds[t] = cmul(lds[t], f <= N / 2 ? e : make_double2(e.x, -e.y));
         }
-        lds[t] = cmul(lds[t], m);
+    } else {
+        double sr, cr;
+        sincospi((double)(2 * k1) / (double)(ll(1) << lgN), &sr, &cr);
+        const double2 r1 = make_double2(cr, -sr);
+        sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
+        const double2 r2 = make_double2(cr, -sr);
+        for (int t = tid; t < N2; t += WG) {
+            double cs, sn, sh;
+            bin_trig_rows(twl, r1, r2, (int)bitrev(t, lg2), cs, sn, sh);
+            lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
+        }
     }
     __syncthreads();
     lds_dit_inv(lds, lg2, 1, twl);
@@ -653,20 +685,26 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N = ll(1) << lgN, N2 = ll(1) << lg2;
-    const int N1 = 1 << lg1, C = NLDS >> lg1;
+    const int N1 = 1 << lg1, lgC = lg2 - lg1, C = 1 << lgC;
     const double invN = 1.0 / (double)N;
     const ll n20 = (ll)tile * C;
     const int tid = threadIdx.x;
+    // loads first (unrolled: several in flight), then the twiddles in place
+#pragma unroll 4
     for (int t = tid; t < NLDS; t += WG) {
-        const int c = t % C, p1 = t / C;
+        const int c = t & (C - 1), p1 = t >> lgC;
+        lds[c * N1 + p1] = j.scr[(ll)p1 * N2 + n20 + c];
+    }
+    for (int t = tid; t < NLDS; t += WG) {  // the same elements, in the same threads
+        const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
         const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
-        lds[c * N1 + p1] = cmulc(j.scr[(ll)p1 * N2 + n2], w);
+        lds[c * N1 + p1] = cmulc(lds[c * N1 + p1], w);
     }
     __syncthreads();
     lds_dit_inv(lds, lg1, C, twl);
     for (int t = tid; t < NLDS; t += WG) {
-        const int c = t % C, n1 = t / C;
+        const int c = t & (C - 1), n1 = t >> lgC;
         const ll idx = (ll)n1 * N2 + n20 + c;
         if (idx >= j.out_off && idx < j.out_off + j.n_out)
             j.dst[idx - j.out_off] = tilt_out(lds[c * N1 + n1].x * invN, j.beta, idx);
@@ -917,15 +955,7 @@ __device__ __forceinline__ void spec_fill(const Mp &p, ll h, int lgN, double2 *o
     const ll N = ll(1) << lgN;
     for (ll f = threadIdx.x; f <= N / 2; f += WG) {
         double cs, sn, sh;
-        if (lgN <= LG_NLDS) {
-            bin_trig_lds(twl, f, lgN, cs, sn, sh);
-        } else {  // lgN = 12: theta = 2 pi f / 4096 from the table, sin(theta / 2) directly
-            const double2 e = twl[f];
-            cs = e.x;
-            sn = -e.y;
-            double c2;
-            sincospi((double)f / (double)N, &sh, &c2);
-        }
+        bin_trig_lds(twl, f, lgN, cs, sn, sh);
         out[f] = kernel_power(q, cs, sn, sh);
     }
 }
@@ -1488,9 +1518,10 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
     const char *s0 = (const char *)a.src, *s1 = (const char *)(a.src + a.n_in);
     const char *d0 = (const char *)a.dst, *d1 = (const char *)(a.dst + a.n_out);
     if (s0 < lo || s1 > hi || d0 < lo || d1 > hi) return false;
+    if (a.kind == K_LDS && a.lgN > lds_lg(prec)) return false;  // must fit the LDS buffer
     if (a.kind == K_4STEP) {
         const char *c0 = (const char *)a.scr, *c1 = (const char *)(a.scr + (ll(1) << a.lgN));
-        if (c0 < lo || c1 > hi || a.lgN <= LG_NLDS) return false;
+        if (c0 < lo || c1 > hi || a.lgN <= lds_lg(prec)) return false;
     }
     return true;
 }
@@ -1694,7 +1725,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     if (lgN < 1) lgN = 1;
     a.lgN = lgN;
     const bool direct = beta == 0.0 && h <= cx.tn.direct_max_h && n_in <= cx.tn.direct_max_n;
-    a.kind = direct ? K_DIRECT : (lgN <= LG_NLDS ? K_LDS : K_4STEP);
+    a.kind = direct ? K_DIRECT : (lgN <= lds_lg(PREC) ? K_LDS : K_4STEP);
     a.prec = direct ? 0 : PREC;  // direct stepping is always FP64
     a.nph = a.kind == K_4STEP ? 3 : 1;
     a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
@@ -1736,17 +1767,22 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
 // threads call; filled on a miss, oldest entry replaced).
 __device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN)
 {
-    if (threadIdx.x == 0) {
+    static_assert(SPC_E <= 64, "one key per lane of wave 0");
+    if (threadIdx.x < 64) {
+        // lane k compares key k; the highest matching entry wins
         const ll key = (h << 8) | lgN;
-        int x = -1;
-        for (int k = 0; k < SPC_E; ++k) x = (cx.sh->spk[k] == key) ? k : x;
-        cx.sh->spf = x < 0;
-        if (x < 0) {
-            x = cx.sh->spn % SPC_E;
-            cx.sh->spn += 1;
-            cx.sh->spk[x] = key;
+        const int l = threadIdx.x;
+        const unsigned long long hit = __ballot(l < SPC_E && cx.sh->spk[l < SPC_E ? l : 0] == key);
+        if (l == 0) {
+            int x = hit ? 63 - __clzll(hit) : -1;
+            cx.sh->spf = x < 0;
+            if (x < 0) {
+                x = cx.sh->spn % SPC_E;
+                cx.sh->spn += 1;
+                cx.sh->spk[x] = key;
+            }
+            cx.sh->spx = x;
         }
-        cx.sh->spx = x;
     }
     __syncthreads();
     const int x = __builtin_amdgcn_readfirstlane(cx.sh->spx);
@@ -2653,7 +2689,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
 solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__restrict__ tw, double *price, ll *bnd,
              ll bnd_stride, int32_t *err, Stats *stats, Pool pl, Tune tn)
 {
-    __shared__ double2 lds[NLDS];
+    __shared__ double2 lds[PREC ? NLDS : NLDS64];  // FFT tiles (mixed: NLDS split-FP32 values)
     __shared__ double2 twl[NLDS + 1];  // e^{-2 pi i t / 4096}, t <= 2048
     __shared__ float4 twf[PREC ? NLDS / 2 : 1];  // split twiddles (mixed precision only)
     __shared__ Frame stk[MAXD];
