@@ -2059,6 +2059,8 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     int sp = 0, tail = 0;
     ll rv = 0;
     int e = DEV_OK;
+    // work counters, kept in registers of lane 0 and added to the LDS ones on return
+    ll n_conv = 0, c_in = 0, c_out = 0, c_pts = 0, b_rows = 0, b_cyc = 0;
     Frame fr = uni_frame(root);
     for (;;) {
         // the frame's pending correlation (job index + 1 in soff) must be done
@@ -2170,8 +2172,8 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             else rv = band_bsm(d, fr.r0, fr.c0, fr.h, fr.c0 + 2 * fr.h, fr.src, fr.dst, cx.bnd, nullptr);
             rv = uni(rv);
             if (l == 0) {
-                cx.st->band_rows += fr.h;
-                cx.st->cyc_band += clk() - tb;
+                b_rows += fr.h;
+                b_cyc += clk() - tb;
             }
         }
         if (!pop && cout > 0) {
@@ -2186,13 +2188,11 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             j.n_out = cout;
             fr.soff = wq_push(q, sp, j, &tail) + 1;
             if (l == 0) {
-                Stats *st = cx.st;
                 const int lg = ceil_log2(cn);
-                st->convs += 1;
-                st->conv_in += cn;
-                st->conv_out += cout;
-                st->fft_points += ll(1) << (lg < 1 ? 1 : lg);
-                st->n_direct += 1;
+                n_conv += 1;
+                c_in += cn;
+                c_out += cout;
+                c_pts += ll(1) << (lg < 1 ? 1 : lg);
             }
         }
         if (pop) {
@@ -2216,7 +2216,17 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             if (so > 0) ok = wq_wait(d, q, k, (int)so - 1, timeout, cx.st);
         }
     }
-    if (e != DEV_OK && l == 0 && *cx.err_sh == 0) *cx.err_sh = e;
+    if (l == 0) {
+        Stats *st = cx.st;
+        st->convs += n_conv;
+        st->n_direct += n_conv;
+        st->conv_in += c_in;
+        st->conv_out += c_out;
+        st->fft_points += c_pts;
+        st->band_rows += b_rows;
+        st->cyc_band += b_cyc;
+        if (e != DEV_OK && *cx.err_sh == 0) *cx.err_sh = e;
+    }
     return rv;
 }
 
