@@ -145,6 +145,20 @@ __device__ ll block_max(ll v, ll *sh)
 // Each pass loads 2^K elements per lane, applies K radix-2 stages in
 // registers and stores them back, so a 2048-point transform takes four LDS
 // round trips.  twl holds e^{-2 pi i t / 4096}, t <= 2048 (LDS).
+// w * e^{-2 pi i p / 2^(t+1)}, p < 2^t <= 4: one of the 8th roots of unity
+// (t and p are constants after unrolling, so this folds to a few operations).
+__device__ __forceinline__ double2 rot_root(double2 w, int t, int p)
+{
+    if (p == 0) return w;
+    if (t == 1 || p == 2) return make_double2(w.y, -w.x);  // times -i
+    const double c = 0.70710678118654752440;            // sqrt(1/2)
+    const double P = c * (w.x + w.y), M = c * (w.y - w.x);
+    return p == 1 ? make_double2(P, M) : make_double2(M, -P);  // times e^{-i pi/4}, e^{-3 i pi/4}
+}
+
+// The twiddle of stage s = s_lo + t for the element at q 2^s_lo + j of its
+// half-block is e^{-2 pi i j / 2^(s+1)} -- one table value per stage and
+// thread -- times a root of unity fixed by q (rot_root).
 template <int K, bool INV>
 __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, const double2 *twl)
 {
@@ -160,18 +174,18 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
         const int j = r & jmask;
         const int blk = r >> s_lo;
         const int base = b * n + (blk << (s_hi + 1)) + j;
-        double2 v[G];
+        double2 v[G], om[K];
 #pragma unroll
         for (int q = 0; q < G; ++q) v[q] = x[base + (q << s_lo)];
+#pragma unroll
+        for (int t = 0; t < K; ++t) om[t] = twl[j << (11 - s_lo - t)];
         if (!INV) {
 #pragma unroll
             for (int t = K - 1; t >= 0; --t) {
-                const int s = s_lo + t;
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     if (q & (1 << t)) continue;
-                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
-                    const double2 w = twl[jj << (11 - s)];
+                    const double2 w = rot_root(om[t], t, q & ((1 << t) - 1));
                     const double2 u = v[q], z = v[q + (1 << t)];
                     v[q] = make_double2(u.x + z.x, u.y + z.y);
                     v[q + (1 << t)] = cmul(make_double2(u.x - z.x, u.y - z.y), w);
@@ -180,12 +194,10 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
         } else {
 #pragma unroll
             for (int t = 0; t < K; ++t) {
-                const int s = s_lo + t;
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     if (q & (1 << t)) continue;
-                    const int jj = ((q & ((1 << t) - 1)) << s_lo) + j;
-                    const double2 w = twl[jj << (11 - s)];
+                    const double2 w = rot_root(om[t], t, q & ((1 << t) - 1));
                     const double2 u = v[q], z = cmulc(v[q + (1 << t)], w);
                     v[q] = make_double2(u.x + z.x, u.y + z.y);
                     v[q + (1 << t)] = make_double2(u.x - z.x, u.y - z.y);
