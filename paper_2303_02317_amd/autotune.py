@@ -91,7 +91,9 @@ def server_table(table: dict | None = None):
     return [(r["model"], r["lg"], r["precision"], r["best"]) for r in tab.get("classes", {}).values()]
 
 
-def time_schedule(ctx, opts, precision, reps=2):
+def time_schedule(ctx, opts, precision, reps=4):
+    """Median wall time of `reps` launches after one warmup (launch times vary by several per cent with the
+    order in which workgroups meet the work pool, so a single best launch ranks schedules poorly)."""
     import torch
 
     from paper_2303_02317_amd import binding
@@ -99,13 +101,13 @@ def time_schedule(ctx, opts, precision, reps=2):
     ws = torch.empty(binding.workspace_bytes(opts, precision), dtype=torch.uint8, device="cuda")
     binding.launch_batch(ctx, opts, precision=precision, workspace=ws)
     torch.cuda.synchronize()
-    best = float("inf")
+    times = []
     for _ in range(reps):
         t0 = time.perf_counter()
         L = binding.launch_batch(ctx, opts, precision=precision, workspace=ws)
         torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
-    return best, L.price.cpu().numpy()
+        times.append(time.perf_counter() - t0)
+    return sorted(times)[len(times) // 2], L.price.cpu().numpy()
 
 
 def tune(ctx, classes=DEFAULT_CLASSES, precision=0, n_options=64, candidates=CANDIDATES, log=print) -> dict:
