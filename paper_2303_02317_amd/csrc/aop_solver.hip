@@ -2073,6 +2073,27 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     int e = DEV_OK;
     // work counters, kept in registers of lane 0 and added to the LDS ones on return
     ll n_conv = 0, c_in = 0, c_out = 0, c_pts = 0, b_rows = 0, b_cyc = 0;
+    // a leaf: the band walk over the trapezoid's rows (ranges already checked)
+    auto walk = [&](const Frame &f) -> ll {
+        const ll tb = clk();
+        ll r;
+        if (d.model == BINOMIAL) r = band_bin(d, f.r0, f.c0, f.h, f.b, f.src, f.dst, cx.bnd, nullptr);
+        else if (d.model == TRINOMIAL) r = band_tri(d, f.r0, f.c0, f.h, f.b, f.src, f.dst, cx.bnd, nullptr);
+        else r = band_bsm(d, f.r0, f.c0, f.h, f.c0 + 2 * f.h, f.src, f.dst, cx.bnd, nullptr);
+        if (l == 0) {
+            b_rows += f.h;
+            b_cyc += clk() - tb;
+        }
+        return uni(r);
+    };
+    // leaf test and its range checks (lattice: red cells [c0, b]; BSM: centred on c0)
+    auto is_leaf = [&](const Frame &f) -> bool {
+        return (d.model != BSM) ? (f.b - f.c0 + 1 <= BAND) : (f.h <= (BAND - 2) / 2);
+    };
+    auto leaf_ok = [&](const Frame &f) -> bool {
+        return (d.model != BSM) ? (in_ws(cx, f.src, f.c0, f.b) && in_ws(cx, f.dst, f.c0, f.c0 + BAND - 1))
+                                : (in_ws(cx, f.src, f.c0 + 1, f.c0 + 2 * f.h) && in_ws(cx, f.dst, f.c0 - f.h, f.c0 + f.h));
+    };
     Frame fr = uni_frame(root);
     for (;;) {
         // the frame's pending correlation (job index + 1 in soff) must be done
@@ -2094,8 +2115,8 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             const ll h1 = h / 2, h2 = h - h1;
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
-                if (nred <= BAND) {
-                    if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + BAND - 1)) e = DEV_RANGE;
+                if (nred <= BAND) {  // only a root can be a leaf: children that are leaves are walked inline
+                    if (!leaf_ok(fr)) e = DEV_RANGE;
                     else leaf = true;
                     pop = true;
                 } else {
@@ -2136,8 +2157,8 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             const ll n = fr.r0, f = fr.c0, h = fr.h;
             const ll h1 = h / 2, h2 = h - h1;
             if (fr.stage == 0) {
-                if (h <= (BAND - 2) / 2) {
-                    if (!in_ws(cx, fr.src, f + 1, f + 2 * h) || !in_ws(cx, fr.dst, f - h, f + h)) e = DEV_RANGE;
+                if (h <= (BAND - 2) / 2) {  // only a root can be a leaf
+                    if (!leaf_ok(fr)) e = DEV_RANGE;
                     else leaf = true;
                     pop = true;
                 } else {
@@ -2177,17 +2198,6 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             }
         }
         if (e != DEV_OK) break;
-        if (leaf) {
-            const ll tb = clk();
-            if (d.model == BINOMIAL) rv = band_bin(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
-            else if (d.model == TRINOMIAL) rv = band_tri(d, fr.r0, fr.c0, fr.h, fr.b, fr.src, fr.dst, cx.bnd, nullptr);
-            else rv = band_bsm(d, fr.r0, fr.c0, fr.h, fr.c0 + 2 * fr.h, fr.src, fr.dst, cx.bnd, nullptr);
-            rv = uni(rv);
-            if (l == 0) {
-                b_rows += fr.h;
-                b_cyc += clk() - tb;
-            }
-        }
         if (!pop && cout > 0) {
             // the stage's correlation goes to the other waves while this one
             // solves the sub-trapezoid that does not depend on it
@@ -2207,10 +2217,20 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
                 c_pts += ll(1) << (lg < 1 ? 1 : lg);
             }
         }
+        // A child that is a leaf is walked right here, after the push above
+        // (so the correlation overlaps it), and this frame stays current for
+        // its next stage; a root that is a leaf is walked the same way.
+        const bool inl = !pop && is_leaf(child);
+        if (inl && !leaf_ok(child)) {
+            e = DEV_RANGE;
+            break;
+        }
+        if (leaf || inl) rv = walk(inl ? child : fr);
         if (pop) {
             if (sp == 0) break;
             --sp;
             fr = uni_frame(wstk[sp]);
+        } else if (inl) {
         } else if (sp + 1 >= cap) {
             e = DEV_STACK;
             break;
