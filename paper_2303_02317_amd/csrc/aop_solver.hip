@@ -2001,7 +2001,6 @@ __device__ __forceinline__ void wq_worker(const Mp &d, WQueue *q, ll timeout_tic
             if (now_ticks() - last > timeout_ticks) stop = 1;
         }
         if (__builtin_amdgcn_readfirstlane(stop)) break;
-        __builtin_amdgcn_s_sleep(1);
     }
 }
 
@@ -2036,7 +2035,6 @@ __device__ __forceinline__ bool wq_wait(const Mp &d, WQueue *q, int slot, int k,
             continue;
         }
         if (now_ticks() - t0 > timeout_ticks) return false;
-        __builtin_amdgcn_s_sleep(1);
     }
 }
 
