@@ -56,7 +56,8 @@ struct PoolHdr {
     uint64_t status;  // options finished (low 32 bits) | launch aborted (bit 32)
     int64_t helper_tiles, helper_busy, helper_idle;
     int64_t abort_info[8];  // first cause of an abort: reason (1 refused job, 2 wait deadline, 3 drain deadline), details
-    int64_t reserved[3];
+    int64_t n_helpers;  // workgroups that have entered the helper loop (arrival rank: home option)
+    int64_t reserved[2];
 };
 static_assert(sizeof(PoolHdr) == 128, "pool header is 128 bytes");
 constexpr int64_t JOB_BYTES = 128;

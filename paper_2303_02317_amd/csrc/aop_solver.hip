@@ -1553,18 +1553,23 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
     const ll t_start = clk();
     ll busy = 0, tiles = 0;
     unsigned rot = blockIdx.x * 37u;
-    // Home driver: the helpers share the drivers out evenly (helper w serves
-    // option w mod n first), so that every option keeps a few helpers of its
-    // own instead of whatever the scan finds; any job may still be claimed.
+    // Home driver: the helpers share the drivers out evenly -- the k-th
+    // workgroup to enter this loop serves option k mod n first -- so that
+    // every option keeps the same number of helpers of its own instead of
+    // whatever the scan finds; any job may still be claimed.
     int home = -1, home_tries = 0;
     const int n_home = (int)(n < MAX_WG ? n : MAX_WG);
+    int rank = 0;
+    if (tid == 0) rank = (int)__hip_atomic_fetch_add(&pl.hdr->n_helpers, (int64_t)1, __ATOMIC_RELAXED, AGENT);
+    rank = __builtin_amdgcn_readfirstlane(rank);
+    const int home_opt = n_home > 0 ? rank % n_home : 0;
     for (;;) {
         if (tid < 64) {
             int msg = 0, ji = -1;  // 0 nothing, 1 tile, 2 exit
             if (home < 0 && home_tries < 64) {
                 ++home_tries;
                 int hd = -1;
-                if (l == 0) hd = __hip_atomic_fetch_add(pl.drivers + (int)(blockIdx.x % (unsigned)n_home), 0, __ATOMIC_RELAXED, AGENT);
+                if (l == 0) hd = __hip_atomic_fetch_add(pl.drivers + home_opt, 0, __ATOMIC_RELAXED, AGENT);
                 hd = __builtin_amdgcn_readfirstlane(hd);
                 if (hd >= 0 && hd != (int)blockIdx.x && hd < pl.n_wg) home = hd;
             }
