@@ -41,6 +41,8 @@ CANDIDATES = [
     dict(pub_min_lg=11, direct_max_h=320, direct_max_n=2048),
     dict(pub_min_lg=12, direct_max_h=448, direct_max_n=2048),
     dict(pub_min_lg=11, direct_max_h=448, direct_max_n=2048),
+    dict(pub_min_lg=10, direct_max_h=320, direct_max_n=2048),
+    dict(pub_min_lg=10, direct_max_h=448, direct_max_n=2048),
 ]
 
 #: Size classes timed by default: the benchmark workloads' (model, log2 T).
