@@ -55,7 +55,9 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         const double m = std::exp(-o.r * dt);
         if (!(p > 0.0 && p < 1.0)) return AOP_EPROB;
         d.a = a;
-        d.no_green = (o.q == 0.0);
+        // Lemma 2.3: with Y = 0 and R >= 0 no cell below the expiry row
+        // exercises; with R < 0 exercise can pay deep in the money.
+        d.no_green = (o.q == 0.0 && o.r >= 0.0);
         d.w0 = m * (1.0 - p);
         d.w1 = m * p;
         d.w2 = 0.0;
@@ -75,7 +77,7 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         const double m = std::exp(-o.r * dt);
         if (!(pu > 0.0 && pd > 0.0 && po >= 0.0)) return AOP_EPROB;
         d.a = A;
-        d.no_green = (o.q == 0.0);
+        d.no_green = (o.q == 0.0 && o.r >= 0.0);  // as for the binomial lattice
         d.w0 = m * pd;
         d.w1 = m * po;
         d.w2 = m * pu;

@@ -5,27 +5,35 @@ for a test run, so its results for the benchmark workloads are stored here:
 
     oracle_<model>_c<config>_t<log2T>.json
 
-Each file holds, per option, the parameters, the American price and the
-oracle's boundary at a fixed set of sampled rows.  Inputs come from
-``paper_2303_02317_amd.inputs.batch(config, log2T, 64, model)``; a file may hold
-only the first k options of the 64 (stated in the file as ``n_options``).
+Each file holds, per option, the parameters, the American price, and at a
+fixed set of sampled rows the oracle's boundary together with its decision
+margins there (the gap at the boundary cell and at the cell after it, in the
+oracle's units: K for the lattices, the nondimensional value for BSM; null
+where the oracle reports none).  Inputs come from
+``paper_2303_02317_amd.inputs.batch(config, log2T, 64, model)``; a file may
+hold only the first k options of the 64 (stated in the file as
+``n_options``).
+
+Options are priced in parallel, one per thread; each finished option is
+cached under ``--cache`` so that an interrupted run resumes where it stopped.
 
 Usage: python tests/golden/make_golden.py [--threads N] [--only name ...]
+                                          [--cache DIR]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
+import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
-
-import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
 from paper_2303_02317_amd import inputs  # noqa: E402
@@ -36,10 +44,10 @@ JOBS = [
     ("trinomial", 1, 3, 16, 64),
     ("bsm", 2, 4, 16, 64),
     ("binomial", 0, 2, 17, 64),
-    ("trinomial", 1, 3, 18, 24),
-    ("bsm", 2, 4, 18, 24),
-    ("binomial", 0, 2, 20, 12),
-    ("trinomial", 1, 3, 20, 6),
+    ("bsm", 2, 4, 18, 64),
+    ("trinomial", 1, 3, 18, 64),
+    ("binomial", 0, 2, 20, 64),
+    ("trinomial", 1, 3, 20, 24),
 ]
 
 
@@ -50,35 +58,62 @@ def sample_rows(T: int) -> list[int]:
     return sorted(r for r in rows if 0 <= r <= T)
 
 
+def _num(x: float):
+    return float(x) if math.isfinite(x) else (None if math.isnan(x) else ("-inf" if x < 0 else "inf"))
+
+
 def run_one(opt):
     t0 = time.time()
-    price, b, _ = oracle.price_option(opt, boundary=True)
+    price, b, mg = oracle.price_option(opt, boundary=True, margin=True)
     dt = time.time() - t0
     rows = sample_rows(opt["T"])
-    return dict(params=opt, price=price, seconds=dt,
-                boundary_rows=rows, boundary=[int(b[r]) for r in rows])
+    return dict(params=opt, price=price, seconds=dt, boundary_rows=rows,
+                boundary=[int(b[r]) for r in rows],
+                margin=[[_num(mg[2 * r]), _num(mg[2 * r + 1])] for r in rows])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=len(os.sched_getaffinity(0)))
     ap.add_argument("--only", nargs="*", default=None)
+    ap.add_argument("--cache", default=os.path.join(ROOT, "_work", "golden_cache"))
     args = ap.parse_args()
     oracle.build()
+    os.makedirs(args.cache, exist_ok=True)
+    lock = threading.Lock()
     for name, model, cfg, log2T, n in JOBS:
         fname = "oracle_%s_c%d_t%d.json" % (name, cfg, log2T)
         if args.only and fname not in args.only and name not in args.only:
             continue
         path = os.path.join(HERE, fname)
         if os.path.exists(path):
-            continue
+            doc = json.load(open(path))
+            if doc.get("n_options", 0) >= n and all("margin" in r for r in doc["options"]):
+                continue
+        cache = os.path.join(args.cache, fname + ".jsonl")
+        done = {}
+        if os.path.exists(cache):
+            for line in open(cache):
+                rec = json.loads(line)
+                done[rec["index"]] = rec["record"]
         opts = inputs.batch(cfg, log2T, 64, model)[:n]
+        todo = [k for k in range(n) if k not in done]
         t0 = time.time()
+
+        def work(k):
+            rec = run_one(opts[k])
+            with lock:
+                with open(cache, "a") as f:
+                    f.write(json.dumps(dict(index=k, record=rec)) + "\n")
+                print("%s option %d: %.1fs" % (fname, k, rec["seconds"]), flush=True)
+            return k, rec
+
         with ThreadPoolExecutor(max_workers=args.threads) as ex:
-            recs = list(ex.map(run_one, opts))
+            for k, rec in ex.map(work, todo):
+                done[k] = rec
         doc = dict(model=model, config=cfg, log2T=log2T, T=1 << log2T, n_options=n,
                    seed=[cfg, log2T], lam=oracle.DEFAULT_LAMBDA, threads=args.threads,
-                   wall_seconds=time.time() - t0, options=recs)
+                   wall_seconds=time.time() - t0, options=[done[k] for k in range(n)])
         with open(path + ".tmp", "w") as f:
             json.dump(doc, f, indent=1)
         os.replace(path + ".tmp", path)

@@ -17,6 +17,7 @@ ABS_FP64_K = 1e-13
 REL_MIXED = 1e-6
 ABS_MIXED_K = 1e-9
 TIE = 1e-9
+BSM_NONE = int(np.iinfo(np.int64).min)
 
 
 def price_ok(got, ref, K, rel_tol=REL_FP64, abs_tol_k=ABS_FP64_K):
@@ -33,8 +34,21 @@ def price_errors(got, ref):
     return err, err / max(abs(ref), 1e-300)
 
 
+def golden_margins(rec):
+    """Decision margins stored with a golden record (see tests/golden/make_golden.py),
+    flattened as the oracle returns them (2 per sampled row), or None."""
+    if "margin" not in rec:
+        return None
+    conv = {None: np.nan, "inf": np.inf, "-inf": -np.inf}
+    return np.array([conv[v] if v is None or isinstance(v, str) else float(v)
+                     for pair in rec["margin"] for v in pair], dtype=np.float64)
+
+
 def boundary_mismatches(gb, ob, margin, model, T):
-    """Rows where the GPU boundary differs from the oracle's other than by a near-tie."""
+    """Rows where the GPU boundary differs from the oracle's other than by a near-tie.
+
+    The BSM sentinel INT64_MIN ("no exercise cell") only ever equals itself:
+    indices are compared as Python integers, so no difference overflows."""
     bad = []
     rows = np.nonzero(np.asarray(gb) != np.asarray(ob))[0]
     for i in rows:

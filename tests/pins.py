@@ -193,3 +193,158 @@ def grid_binomial(S, K, r, q, sigma, E, T):
         red[i, :i + 1] = c >= e
         G[i, :i + 1] = np.where(c >= e, c, e)
     return G, red
+
+
+def mp_trinomial(S, K, r, q, sigma, E, T, american=True, dps=50):
+    """Trinomial lattice of Sec. 3 evaluated in mpmath at ``dps`` digits."""
+    with mpmath.workdps(dps):
+        S, K, r, q, sigma, E = (mpmath.mpf(x) for x in (S, K, r, q, sigma, E))
+        dt = E / T
+        A = sigma * mpmath.sqrt(2 * dt)
+        su, sd = mpmath.e ** (A / 2), mpmath.e ** (-A / 2)
+        g = mpmath.e ** ((r - q) * dt / 2)
+        pu = ((g - sd) / (su - sd)) ** 2
+        pd = ((su - g) / (su - sd)) ** 2
+        po = 1 - pu - pd
+        m = mpmath.e ** (-r * dt)
+        u = mpmath.e ** A
+        row = [max(S * u ** (j - T) - K, 0) for j in range(2 * T + 1)]
+        for i in range(T - 1, -1, -1):
+            new = []
+            for j in range(2 * i + 1):
+                c = m * (pd * row[j] + po * row[j + 1] + pu * row[j + 2])
+                new.append(max(c, S * u ** (j - i) - K) if american else c)
+            row = new
+        return float(row[0])
+
+
+def grid_trinomial(S, K, r, q, sigma, E, T):
+    """Full trinomial grid (row i: columns 0..2i) and red mask, row by row (numpy)."""
+    import numpy as np
+
+    _, u, pu, po, pd, m = topm_params(r, q, sigma, E, T)
+    G = np.full((T + 1, 2 * T + 1), np.nan)
+    red = np.zeros((T + 1, 2 * T + 1), dtype=bool)
+    j = np.arange(2 * T + 1)
+    e = S * u ** (j - float(T)) - K
+    G[T] = np.maximum(e, 0.0)
+    red[T] = 0.0 >= e
+    for i in range(T - 1, -1, -1):
+        w = 2 * i + 1
+        j = np.arange(w)
+        c = m * pd * G[i + 1, :w] + m * po * G[i + 1, 1:w + 1] + m * pu * G[i + 1, 2:w + 2]
+        e = S * u ** (j - float(i)) - K
+        red[i, :w] = c >= e
+        G[i, :w] = np.where(c >= e, c, e)
+    return G, red
+
+
+def grid_bsm_put(S, K, r, sigma, E, T, lam=1.0 / 3.0):
+    """Full explicit BSM grid on the apex's cone and its exercise mask (numpy).
+
+    Row n (n = 0 at expiry, T at the apex) holds offsets k = -T..T at column
+    k + T; only |k| <= T - n is defined.  Returns (V, green) with green[n, k+T]
+    true where the exercise value exceeds the continuation value.
+    """
+    import numpy as np
+
+    a, b, c, ds, _ = bsm_coeffs(r, sigma, E, T, lam)
+    s0 = math.log(S / K)
+    k = np.arange(-T, T + 1)
+    g = 1.0 - np.exp(s0 + k * ds)
+    V = np.full((T + 1, 2 * T + 1), np.nan)
+    green = np.zeros((T + 1, 2 * T + 1), dtype=bool)
+    V[0] = np.maximum(g, 0.0)
+    green[0] = g > 0.0
+    for n in range(1, T + 1):
+        lo, hi = n, 2 * T - n  # columns of |k| <= T - n
+        cont = b * V[n - 1, lo - 1:hi] + c * V[n - 1, lo:hi + 1] + a * V[n - 1, lo + 1:hi + 2]
+        gg = g[lo:hi + 1]
+        green[n, lo:hi + 1] = gg > cont
+        V[n, lo:hi + 1] = np.where(gg > cont, gg, cont)
+    return V, green
+
+
+# ----------------------------------------- brute-force exercise decisions
+def _decisions_to_boundary(red_at, green_at, T, width, lattice=True):
+    """Per-row boundary from node decisions recorded along every tree path.
+
+    Lattices: last red column of each row (-1 if none).  BSM: last green
+    offset (None if none).  A row whose decisions disagree between paths (a
+    rounding-level tie reached by differently rounded products) is None.
+    """
+    out = []
+    for t in range(T + 1):
+        cols = range(width(t))
+        amb = any((t, j) in red_at and (t, j) in green_at for j in cols)
+        if amb:
+            out.append("tie")
+            continue
+        if lattice:
+            reds = [j for j in cols if (t, j) in red_at]
+            out.append(max(reds) if reds else -1)
+        else:
+            greens = [j for j in cols if (t, j) in green_at]
+            out.append(max(greens) if greens else None)
+    return out
+
+
+def brute_binomial_boundary(S, K, r, q, sigma, E, T):
+    """Boundary of each row from a non-recombining tree walked path by path.
+
+    Node (t, j) is reached after j up moves; its price is carried along the
+    path by multiplying with u or d.  Returns (price, boundary list)."""
+    _, u, d, p, m = bopm_params(r, q, sigma, E, T)
+    red_at, green_at = set(), set()
+
+    def value(t, j, x):
+        ex = x - K
+        if t == T:
+            (red_at if 0.0 >= ex else green_at).add((t, j))
+            return max(ex, 0.0)
+        cont = m * (p * value(t + 1, j + 1, x * u) + (1.0 - p) * value(t + 1, j, x * d))
+        (red_at if cont >= ex else green_at).add((t, j))
+        return max(cont, ex)
+
+    price = value(0, 0, S)
+    return price, _decisions_to_boundary(red_at, green_at, T, lambda t: t + 1)
+
+
+def brute_trinomial_boundary(S, K, r, q, sigma, E, T):
+    """As brute_binomial_boundary for the trinomial tree (children j, j+1, j+2)."""
+    _, u, pu, po, pd, m = topm_params(r, q, sigma, E, T)
+    red_at, green_at = set(), set()
+
+    def value(t, j, x):
+        ex = x - K
+        if t == T:
+            (red_at if 0.0 >= ex else green_at).add((t, j))
+            return max(ex, 0.0)
+        cont = m * (pu * value(t + 1, j + 2, x * u) + po * value(t + 1, j + 1, x) + pd * value(t + 1, j, x / u))
+        (red_at if cont >= ex else green_at).add((t, j))
+        return max(cont, ex)
+
+    price = value(0, 0, S)
+    return price, _decisions_to_boundary(red_at, green_at, T, lambda t: 2 * t + 1)
+
+
+def brute_bsm_put_boundary(S, K, r, sigma, E, T, lam=1.0 / 3.0):
+    """Exercise decisions of the explicit scheme walked path by path from the apex.
+
+    Returns (price, boundary) with boundary[n] the last exercise offset k of
+    step n (n = 0 at expiry), None if none, "tie" if paths disagree."""
+    a, b, c, ds, _ = bsm_coeffs(r, sigma, E, T, lam)
+    red_at, green_at = set(), set()
+
+    def value(n, k, s):  # n = steps to expiry left, k = offset from the apex
+        g = 1.0 - math.exp(s)
+        if n == 0:
+            (green_at if g > 0.0 else red_at).add((n, k + T))
+            return max(g, 0.0)
+        cont = b * value(n - 1, k - 1, s - ds) + c * value(n - 1, k, s) + a * value(n - 1, k + 1, s + ds)
+        (green_at if g > cont else red_at).add((n, k + T))
+        return max(cont, g)
+
+    price = K * value(T, 0, math.log(S / K))
+    bnd = _decisions_to_boundary(red_at, green_at, T, lambda n: 2 * T + 1, lattice=False)
+    return price, [x - T if isinstance(x, int) else x for x in bnd]

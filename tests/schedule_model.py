@@ -123,7 +123,7 @@ class Model:
     def __init__(self, opt, lam=1.0 / 3.0):
         self.d = params(opt, lam)
         self.T = opt["T"]
-        self.no_green = opt["model"] != BSM and opt["q"] == 0.0
+        self.no_green = opt["model"] != BSM and opt["q"] == 0.0 and opt["r"] >= 0.0
         self.bnd = np.full(self.T + 1, -7, dtype=np.int64)
         self.max_depth = 0
         self.ffts = []  # (N, h)

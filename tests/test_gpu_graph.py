@@ -1,12 +1,14 @@
 """GPU test of the hipGraph form of a batch launch (aop_graph_*).
 
 The graph is replayed several times with eager work and synchronisations in
-between; every replay must reproduce the eager prices bitwise.
+between; every replay must reproduce the eager prices bitwise, and those
+prices must match the CPU oracle.
 """
 import numpy as np
 import pytest
 
 from paper_2303_02317_amd import inputs
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +27,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replays_match_eager(ctx, precision):
+def test_graph_replays_match_eager(ctx, oracle_mod, precision):
     import torch
 
     from paper_2303_02317_amd import binding
@@ -35,6 +37,10 @@ def test_graph_replays_match_eager(ctx, precision):
         opts += inputs.batch(780 + m, 13, 4, m, T=3000 + 2000 * m)
     ref, st, rb = binding.price_batch(ctx, opts, precision=precision, boundary=True)
     assert (st == 0).all()
+    rel, ak = (parity.REL_FP64, parity.ABS_FP64_K) if precision == 0 else (parity.REL_MIXED, parity.ABS_MIXED_K)
+    for i, (o, (orc, ob, mg)) in enumerate(zip(opts, oracle_mod.price_many(opts, boundary=True, margin=True))):
+        assert parity.price_ok(ref[i], orc, o["K"], rel, ak), (o, ref[i], orc)
+        assert not parity.boundary_mismatches(rb[i][:o["T"] + 1], ob, mg, o["model"], o["T"])
     g = binding.BatchGraph(ctx, opts, precision=precision, boundary=True)
     other = inputs.batch(790, 11, 5, 1)
     for k in range(8):

@@ -84,7 +84,8 @@ def test_mixed_close_to_fp64_path(ctx):
         assert mixed_ok(pmx[k], p64[k], o["K"]), (o, pmx[k], p64[k])
 
 
-GOLDEN = ["oracle_trinomial_c3_t16.json", "oracle_bsm_c4_t16.json", "oracle_binomial_c2_t17.json"]
+GOLDEN = ["oracle_trinomial_c3_t16.json", "oracle_bsm_c4_t16.json", "oracle_binomial_c2_t17.json",
+          "oracle_trinomial_c3_t18.json", "oracle_bsm_c4_t18.json", "oracle_trinomial_c3_t20.json"]
 
 
 @pytest.mark.parametrize("fname", GOLDEN)
@@ -93,11 +94,20 @@ def test_mixed_golden(ctx, fname):
     doc = json.load(open(path))
     recs = doc["options"]
     opts = [r["params"] for r in recs]
-    p, st, _ = run_mixed(ctx, opts, boundary=False)
+    p, st, b = run_mixed(ctx, opts, boundary=True)
     fails, rels = [], []
     for k, r in enumerate(recs):
         o = r["params"]
+        assert st[k] == 0, (k, st[k])
         ae, re = parity.price_errors(p[k], r["price"])
+        say("%s option %d: price %.12g abs/K %.2e rel %.2e" % (fname, k, r["price"], ae / o["K"], re))
+        mg = parity.golden_margins(r)
+        if mg is not None:
+            rows = np.asarray(r["boundary_rows"])
+            bad = parity.boundary_mismatches(b[k][rows], np.asarray(r["boundary"], dtype=np.int64), mg,
+                                             o["model"], o["T"])
+            if bad:
+                fails.append(("boundary", k, bad[:5]))
         if abs(r["price"]) >= 1e-3 * o["K"]:
             rels.append(re)
         if not mixed_ok(p[k], r["price"], o["K"]):

@@ -33,6 +33,15 @@ MUTATIONS = {
     "bsm_drift_sign_b": ("const double cb = lam - drift;", "const double cb = lam + drift;"),
     "bsm_dropped_discount_term": ("const double cc = 1.0 - omega * dtau - 2.0 * lam;",
                                   "const double cc = 1.0 - 2.0 * lam;"),
+    "guard_dropped_in_red_test": ("    return (c >= e) && isfinite(c) && isfinite(e);", "    return (c >= e);"),
+    "guard_dropped_binomial_loop": ("double e = S * X[2 * j - i + T] - K;\n                int red = (c >= e) & (c < INFINITY) & (e < INFINITY);",
+                                    "double e = S * X[2 * j - i + T] - K;\n                int red = (c >= e);"),
+    "guard_dropped_trinomial_loop": ("double e = S * X[j - i + T] - K;\n                int red = (c >= e) & (c < INFINITY) & (e < INFINITY);",
+                                     "double e = S * X[j - i + T] - K;\n                int red = (c >= e);"),
+    "bsm_boundary_off_by_one": ("lastg = green ? k : lastg;", "lastg = green ? k - 1 : lastg;"),
+    "bsm_boundary_off_by_one_margin_path": ("if (green) lastg = k;\n            }", "if (green) lastg = k - 1;\n            }"),
+    "binomial_boundary_off_by_one": ("last = red ? j : last;\n            }\n        } else {\n            for (int64_t j = 0; j <= i; ++j)",
+                                     "last = red ? j - 1 : last;\n            }\n        } else {\n            for (int64_t j = 0; j <= i; ++j)"),
     "bsm_payoff_shift": ("double g = 1.0 - EX[k + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg",
                          "double g = 1.0 - EX[k + 1 + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg"),
 }
@@ -64,6 +73,27 @@ def _battery(oracle_mod, lib):
             fails.append("tie rule")
         if abs(P(2, 100.0, 110.0, 0.05, 0.0, 0.25, 1.0, 1000, american=False) - pins.bs_put(100.0, 110.0, 0.05, 0.25, 1.0)) > 2e-3 * 110:
             fails.append("bsm limit")
+        # overflowing lattice tops (sigma sqrt(E T) > 709.8) against high precision
+        for model, ref in ((0, pins.mp_binomial), (1, pins.mp_trinomial)):
+            ov = (100.0, 100.0, 0.05, 0.03, 80.0, 1.0, 96)
+            exact = ref(*ov)
+            for kw in ({}, dict(boundary=True, margin=True)):
+                got = P(model, *ov, **kw)
+                got = got[0] if isinstance(got, tuple) else got
+                if not (math.isfinite(got) and abs(got - exact) <= 1e-13 * exact):
+                    fails.append("overflow pin")
+        # boundaries against decisions recorded on brute-force trees
+        none = np.iinfo(np.int64).min
+        for T in (6, 8):
+            for kw in (dict(boundary=True), dict(boundary=True, margin=True)):
+                _, ref = pins.brute_binomial_boundary(*prm, T)
+                b = P(0, *prm, T, **kw)[1]
+                if any(x != "tie" and int(b[i]) != x for i, x in enumerate(ref)):
+                    fails.append("binomial boundary")
+                _, ref = pins.brute_bsm_put_boundary(90.0, 110.0, 0.08, 0.45, 2.0, T)
+                b = P(2, 90.0, 110.0, 0.08, 0.0, 0.45, 2.0, T, **kw)[1]
+                if any(x != "tie" and int(b[i]) != (none if x is None else x) for i, x in enumerate(ref)):
+                    fails.append("bsm boundary")
     except oracle_mod.OracleError:
         fails.append("rejected a valid option")
     return fails

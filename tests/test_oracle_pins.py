@@ -271,3 +271,161 @@ def test_tie_rule_is_red(oracle_mod):
     for T in (2, 200, 2000):
         _, b, mg = oracle_mod.price(B, 100.0, 100.0, 0.05, 0.03, 0.2, 1.0, T, boundary=True, margin=True)
         assert b[T] == T // 2 and mg[2 * T] == 0.0
+
+
+# ------------------------------------------------- non-finite guard (overflow)
+OVERFLOW = [
+    # sigma sqrt(E T) > 709.8: the top of the lattice overflows to +inf in FP64
+    (100.0, 100.0, 0.05, 0.03, 80.0, 1.0, 96),
+    (120.0, 90.0, 0.06, 0.02, 60.0, 1.5, 120),
+    (100.0, 100.0, 0.05, 0.0, 80.0, 1.0, 96),   # q = 0: no exercise in exact arithmetic
+    (100.0, 100.0, 0.03, 0.06, 75.0, 1.0, 100),
+]
+
+
+@pytest.mark.parametrize("prm", OVERFLOW)
+def test_overflowing_lattice_against_high_precision(oracle_mod, prm):
+    # Cells whose exercise value overflows are exercise cells (the guard of
+    # Definition 2.1's red test).  They lie where the risk-neutral weight of
+    # reaching them is far below 1e-300, so the FP64 price still equals the
+    # exact lattice value; without the guard inf >= inf marks them red and the
+    # infinity reaches the root.
+    S, K, r, q, s, E, T = prm
+    assert s * math.sqrt(E * T) > 709.8
+    for model, ref in ((B, pins.mp_binomial), (TR, pins.mp_trinomial)):
+        exact = ref(S, K, r, q, s, E, T)
+        got = oracle_mod.price(model, S, K, r, q, s, E, T)
+        got_m, _, _ = oracle_mod.price(model, S, K, r, q, s, E, T, boundary=True, margin=True)
+        assert math.isfinite(got) and abs(got - exact) <= 1e-13 * exact
+        assert got_m == got
+
+
+def test_trinomial_high_precision(oracle_mod):
+    for prm in PARAMS_SMALL:
+        S, K, r, q, s, E = prm
+        got = oracle_mod.price(TR, S, K, r, q, s, E, 60)
+        ref = pins.mp_trinomial(S, K, r, q, s, E, 60)
+        assert abs(got - ref) <= 1e-13 * max(1.0, ref)
+
+
+# ------------------------------------------------ negative rate, no dividend
+@pytest.mark.parametrize("model", [B, TR])
+def test_negative_rate_no_dividend_exercises(oracle_mod, model):
+    # With R < 0 and Y = 0 the no-exercise lemma (which needs R > 0) does not
+    # apply: deep in the money, exercising now beats holding.  Brute force on
+    # small trees and the immediate-exercise value pin the oracle there.
+    prm = (150.0, 60.0, -0.03, 0.0, 0.15, 2.0)
+    brute = pins.brute_binomial if model == B else pins.brute_trinomial
+    for T in (5, 8):
+        got = oracle_mod.price(model, *prm, T)
+        assert abs(got - brute(*prm, T)) <= 1e-12 * got
+    am = oracle_mod.price(model, *prm, 400)
+    eu = oracle_mod.price(model, *prm, 400, american=False)
+    assert am == pytest.approx(150.0 - 60.0, abs=1e-12) and eu < am - 1.0
+
+
+# ------------------------------------------------------ boundary references
+BPRM = [
+    (120.0, 100.0, 0.08, 0.06, 0.3, 1.5),
+    (100.0, 100.0, 0.05, 0.03, 0.2, 1.0),
+    (140.0, 60.0, 0.01, 0.06, 0.1, 2.0),
+    (90.0, 105.0, 0.02, 0.05, 0.45, 0.5),
+]
+
+
+def _cmp_rows(got, ref, skip=()):
+    bad = [(i, int(got[i]), ref[i]) for i in range(len(ref)) if i not in skip and ref[i] != "tie"
+           and int(got[i]) != ref[i]]
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("prm", BPRM)
+def test_lattice_boundary_against_brute_force_decisions(oracle_mod, prm):
+    # Each node's red/green decision recorded along every path of a
+    # non-recombining tree gives every row's boundary independently of the
+    # oracle's in-place sweep.
+    for T in (4, 9, 11):
+        _, ref = pins.brute_binomial_boundary(*prm, T)
+        _, b, _ = oracle_mod.price(B, *prm, T, boundary=True)
+        _cmp_rows(b, ref)
+    for T in (3, 6):
+        _, ref = pins.brute_trinomial_boundary(*prm, T)
+        _, b, _ = oracle_mod.price(TR, *prm, T, boundary=True)
+        _cmp_rows(b, ref)
+
+
+@pytest.mark.parametrize("prm", [(90.0, 110.0, 0.08, 0.45, 2.0), (100.0, 100.0, 0.05, 0.2, 1.0),
+                                 (60.0, 140.0, 0.06, 0.3, 1.0), (70.0, 80.0, 0.07, 0.15, 2.0)])
+def test_bsm_boundary_against_brute_force_decisions(oracle_mod, prm):
+    S, K, r, s, E = prm
+    none = np.iinfo(np.int64).min
+    for T in (3, 6, 8):
+        _, ref = pins.brute_bsm_put_boundary(S, K, r, s, E, T)
+        _, b, _ = oracle_mod.price(P, S, K, r, 0.0, s, E, T, boundary=True)
+        ref = [none if x is None else x for x in ref]
+        _cmp_rows(b, ref)
+
+
+@pytest.mark.parametrize("model", [TR, P])
+def test_boundary_against_full_numpy_grid(oracle_mod, model):
+    # The oracle's recorded boundary equals the last red column (lattices) or
+    # last exercise offset (BSM) of a full numpy grid, row by row.
+    rng = np.random.default_rng([108, model])
+    T = 200
+    for _ in range(5):
+        p = inputs.draw_params(rng, model)
+        _, b, mg = oracle_mod.price(model, p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T,
+                                    boundary=True, margin=True)
+        if model == TR:
+            G, red = pins.grid_trinomial(p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T)
+            for i in range(T + 1):
+                reds = np.nonzero(red[i, :2 * i + 1])[0]
+                ref = int(reds.max()) if reds.size else -1
+                if b[i] != ref:
+                    assert _near_tie(mg, 2 * i) or _near_tie(mg, 2 * i + 1), (i, b[i], ref)
+        else:
+            V, green = pins.grid_bsm_put(p["S0"], p["K"], p["r"], p["sigma"], p["expiry"], T)
+            for n in range(T + 1):
+                gs = np.nonzero(green[n])[0]
+                ref = int(gs.max()) - T if gs.size else np.iinfo(np.int64).min
+                if b[n] != ref:
+                    assert _near_tie(mg, 2 * n) or _near_tie(mg, 2 * n + 1), (n, b[n], ref)
+
+
+def test_binomial_boundary_against_full_numpy_grid(oracle_mod):
+    rng = np.random.default_rng([108, B])
+    T = 240
+    for _ in range(5):
+        p = inputs.draw_params(rng, B)
+        _, b, mg = oracle_mod.price(B, p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T,
+                                    boundary=True, margin=True)
+        G, red = pins.grid_binomial(p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T)
+        for i in range(T + 1):
+            reds = np.nonzero(red[i, :i + 1])[0]
+            ref = int(reds.max()) if reds.size else -1
+            if b[i] != ref:
+                assert _near_tie(mg, 2 * i) or _near_tie(mg, 2 * i + 1), (i, b[i], ref)
+
+
+# ---------------------------------------------- survey-time cross-check values
+def test_survey_cross_check_values(oracle_mod):
+    # Values computed independently (throwaway numpy) when the path was
+    # surveyed, at the single-option point (S = K = 100, R = 0.05, Y = 0.03,
+    # V = 0.2, E = 1 year) unless stated.
+    cfg1 = (100.0, 100.0, 0.05, 0.03, 0.2, 1.0)
+    p, b, _ = oracle_mod.price(B, *cfg1, 2000, boundary=True)
+    assert p == pytest.approx(8.65179401413394, rel=1e-13)
+    assert list(b[:6]) == [0, 1, 2, 3, 4, 5] and b[1998] == 1056 and b[1999] == 1056 and b[2000] == 1000
+    assert oracle_mod.price(B, *cfg1, 2000, american=False) == pytest.approx(8.65156725043792, rel=1e-13)
+    p, b, _ = oracle_mod.price(TR, *cfg1, 2000, boundary=True)
+    assert p == pytest.approx(8.65227509654429, rel=1e-13) and b[1999] == 2079
+    assert oracle_mod.price(TR, *cfg1, 2000, american=False) == pytest.approx(8.65204788716948, rel=1e-13)
+    bsm = (100.0, 100.0, 0.05, 0.0, 0.2, 1.0)
+    assert oracle_mod.price(P, *bsm, 2000) == pytest.approx(6.09033225614848, rel=1e-13)
+    assert oracle_mod.price(P, *bsm, 2000, american=False) == pytest.approx(5.57329504835891, rel=1e-13)
+    for T, v in ((1, 10.53727992187781), (2, 7.777507797933374), (5, 9.033635181083387),
+                 (12, 8.494212397930681)):
+        assert oracle_mod.price(B, *cfg1, T) == pytest.approx(v, rel=1e-14)
+    d = (oracle_mod.price(TR, 110.0, 100.0, 0.08, 0.02, 0.3, 1.5, 500, american=False) -
+         oracle_mod.price(B, 110.0, 100.0, 0.08, 0.02, 0.3, 1.5, 1000, american=False))
+    assert abs(d) <= 1e-11
