@@ -56,6 +56,9 @@ static int is_red(double c, double e)
  * boundary[i] = last red column of row i (or -1), i = 0..T.
  * margin[2i]   = (c-e)/K at the last red cell of row i (NAN if none),
  * margin[2i+1] = (e-c)/K at the cell right after it (NAN if none).
+ * Below row T the two gaps are kept as the row is swept (the gap of the last
+ * red cell seen so far and of the cell right after it), so recording them
+ * costs no extra array traffic.
  * (Margins are decision gaps in units of the strike; -inf marks non-finite.)
  */
 static int oracle_binomial(double S, double K, double r, double q, double sigma, double E,
@@ -100,6 +103,7 @@ static int oracle_binomial(double S, double K, double r, double q, double sigma,
 
     /* Rows T-1 .. 0, in place: G[j] <- f(G[j], G[j+1]).  The three loop
      * bodies are the same recurrence; they differ only in what they record. */
+    double gap_last = NAN, gap_next = NAN; /* decision gaps at the last red cell and the next */
     for (int64_t i = T - 1; i >= 0; --i) {
         last = -1;
         if (!american) {
@@ -114,19 +118,23 @@ static int oracle_binomial(double S, double K, double r, double q, double sigma,
                 last = red ? j : last;
             }
         } else {
+            int prev_red = 1; /* column -1 counts as red: with no red cell the next cell is column 0 */
             for (int64_t j = 0; j <= i; ++j) {
                 double c = w_dn * G[j] + w_up * G[j + 1];
                 double e = S * X[2 * j - i + T] - K;
                 int red = is_red(c, e);
-                D[j] = (isfinite(c) && isfinite(e)) ? (c - e) / K : -INFINITY;
+                double gap = (isfinite(c) && isfinite(e)) ? (c - e) / K : -INFINITY;
                 G[j] = red ? c : e;
-                if (red) last = j;
+                last = red ? j : last;
+                gap_last = red ? gap : gap_last;
+                gap_next = (!red && prev_red) ? -gap : gap_next; /* the cell after a red one */
+                prev_red = red;
             }
         }
         if (boundary) boundary[i] = american ? last : -1;
         if (margin && american) {
-            margin[2 * i] = last >= 0 ? D[last] : NAN;
-            margin[2 * i + 1] = (last + 1 <= i) ? -D[last + 1] : NAN;
+            margin[2 * i] = last >= 0 ? gap_last : NAN;
+            margin[2 * i + 1] = (last + 1 <= i) ? gap_next : NAN;
         }
     }
     *price = G[0];
@@ -180,6 +188,7 @@ static int oracle_trinomial(double S, double K, double r, double q, double sigma
         margin[2 * T + 1] = (last + 1 <= 2 * T) ? -D[last + 1] / K : NAN;
     }
 
+    double gap_last = NAN, gap_next = NAN; /* decision gaps at the last red cell and the next */
     for (int64_t i = T - 1; i >= 0; --i) {
         last = -1;
         if (!american) {
@@ -194,19 +203,23 @@ static int oracle_trinomial(double S, double K, double r, double q, double sigma
                 last = red ? j : last;
             }
         } else {
+            int prev_red = 1; /* column -1 counts as red: with no red cell the next cell is column 0 */
             for (int64_t j = 0; j <= 2 * i; ++j) {
                 double c = w_d * G[j] + w_o * G[j + 1] + w_u * G[j + 2];
                 double e = S * X[j - i + T] - K;
                 int red = is_red(c, e);
-                D[j] = (isfinite(c) && isfinite(e)) ? (c - e) / K : -INFINITY;
+                double gap = (isfinite(c) && isfinite(e)) ? (c - e) / K : -INFINITY;
                 G[j] = red ? c : e;
-                if (red) last = j;
+                last = red ? j : last;
+                gap_last = red ? gap : gap_last;
+                gap_next = (!red && prev_red) ? -gap : gap_next; /* the cell after a red one */
+                prev_red = red;
             }
         }
         if (boundary) boundary[i] = american ? last : -1;
         if (margin && american) {
-            margin[2 * i] = last >= 0 ? D[last] : NAN;
-            margin[2 * i + 1] = (last + 1 <= 2 * i) ? -D[last + 1] : NAN;
+            margin[2 * i] = last >= 0 ? gap_last : NAN;
+            margin[2 * i + 1] = (last + 1 <= 2 * i) ? gap_next : NAN;
         }
     }
     *price = G[0];
@@ -266,6 +279,7 @@ static int oracle_bsm_put(double S, double K, double r, double q, double sigma, 
         margin[1] = (lastg != INT64_MIN && lastg + 1 <= T) ? -D[lastg + 1 + T] : NAN;
     }
 
+    double gap_last = NAN, gap_next = NAN; /* decision gaps at the last green cell and the next */
     for (int64_t n = 1; n <= T; ++n) {
         const int64_t lo = -(T - n), hi = T - n;
         lastg = INT64_MIN;
@@ -281,19 +295,22 @@ static int oracle_bsm_put(double S, double K, double r, double q, double sigma, 
                 lastg = green ? k : lastg;
             }
         } else {
+            int prev_green = 0;
             for (int64_t k = lo; k <= hi; ++k) {
                 double cont = cb * V[k - 1 + T] + cc * V[k + T] + ca * V[k + 1 + T];
                 double g = 1.0 - EX[k + T];
                 int green = g > cont;
-                D[k + T] = g - cont;
                 Vn[k + T] = green ? g : cont;
-                if (green) lastg = k;
+                lastg = green ? k : lastg;
+                gap_last = green ? g - cont : gap_last;
+                gap_next = (!green && prev_green) ? cont - g : gap_next; /* the cell after a green one */
+                prev_green = green;
             }
         }
         if (boundary) boundary[n] = american ? lastg : INT64_MIN;
         if (margin && american) {
-            margin[2 * n] = lastg != INT64_MIN ? D[lastg + T] : NAN;
-            margin[2 * n + 1] = (lastg != INT64_MIN && lastg + 1 <= hi) ? -D[lastg + 1 + T] : NAN;
+            margin[2 * n] = lastg != INT64_MIN ? gap_last : NAN;
+            margin[2 * n + 1] = (lastg != INT64_MIN && lastg + 1 <= hi) ? gap_next : NAN;
         }
         double *t = V; V = Vn; Vn = t;
     }

@@ -39,9 +39,13 @@ MUTATIONS = {
     "guard_dropped_trinomial_loop": ("double e = S * X[j - i + T] - K;\n                int red = (c >= e) & (c < INFINITY) & (e < INFINITY);",
                                      "double e = S * X[j - i + T] - K;\n                int red = (c >= e);"),
     "bsm_boundary_off_by_one": ("lastg = green ? k : lastg;", "lastg = green ? k - 1 : lastg;"),
-    "bsm_boundary_off_by_one_margin_path": ("if (green) lastg = k;\n            }", "if (green) lastg = k - 1;\n            }"),
-    "binomial_boundary_off_by_one": ("last = red ? j : last;\n            }\n        } else {\n            for (int64_t j = 0; j <= i; ++j)",
-                                     "last = red ? j - 1 : last;\n            }\n        } else {\n            for (int64_t j = 0; j <= i; ++j)"),
+    "bsm_boundary_off_by_one_margin_path": ("                lastg = green ? k : lastg;\n                gap_last", "                lastg = green ? k - 1 : lastg;\n                gap_last"),
+    "binomial_boundary_off_by_one": ("last = red ? j : last;\n            }\n        } else {\n            int prev_red = 1;",
+                                     "last = red ? j - 1 : last;\n            }\n        } else {\n            int prev_red = 1;"),
+    "binomial_boundary_off_by_one_margin_path": ("                last = red ? j : last;\n                gap_last = red ? gap : gap_last;",
+                                                 "                last = red ? j - 1 : last;\n                gap_last = red ? gap : gap_last;"),
+    "binomial_margin_of_wrong_cell": ("                gap_next = (!red && prev_red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : -1;\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)",
+                                      "                gap_next = (!red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : -1;\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)"),
     "bsm_payoff_shift": ("double g = 1.0 - EX[k + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg",
                          "double g = 1.0 - EX[k + 1 + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg"),
 }
@@ -94,6 +98,20 @@ def _battery(oracle_mod, lib):
                 b = P(2, 90.0, 110.0, 0.08, 0.0, 0.45, 2.0, T, **kw)[1]
                 if any(x != "tie" and int(b[i]) != (none if x is None else x) for i, x in enumerate(ref)):
                     fails.append("bsm boundary")
+        # decision gaps at the boundary against a full numpy grid
+        gp = (100.0, 95.0, 0.03, 0.05, 0.25, 1.0)
+        T = 60
+        _, b, mg = P(0, *gp, T, boundary=True, margin=True)
+        G, _ = pins.grid_binomial(*gp, T)
+        _, u, _, pp, m = pins.bopm_params(*gp[2:], T)
+        for i in range(T):
+            j = np.arange(i + 1)
+            gap = (m * (1 - pp) * G[i + 1, :i + 1] + m * pp * G[i + 1, 1:i + 2] - (gp[0] * u ** (2.0 * j - i) - gp[1])) / gp[1]
+            last = int(b[i])
+            if 0 <= last and last + 1 <= i and not (abs(mg[2 * i] - gap[last]) <= 1e-12 and
+                                                    abs(mg[2 * i + 1] + gap[last + 1]) <= 1e-12):
+                fails.append("binomial margins")
+                break
     except oracle_mod.OracleError:
         fails.append("rejected a valid option")
     return fails

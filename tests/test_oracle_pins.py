@@ -429,3 +429,32 @@ def test_survey_cross_check_values(oracle_mod):
     d = (oracle_mod.price(TR, 110.0, 100.0, 0.08, 0.02, 0.3, 1.5, 500, american=False) -
          oracle_mod.price(B, 110.0, 100.0, 0.08, 0.02, 0.3, 1.5, 1000, american=False))
     assert abs(d) <= 1e-11
+
+
+def test_binomial_margins_against_full_numpy_grid(oracle_mod):
+    # The decision gaps the oracle records (used to recognise near-ties in the
+    # parity tests) are (c - e)/K at the last red cell and (e - c)/K at the
+    # cell after it, with c the continuation value of Definition 2.1 computed
+    # from the row below on a full numpy grid.
+    rng = np.random.default_rng([109, B])
+    T = 240
+    for _ in range(4):
+        p = inputs.draw_params(rng, B)
+        S, K = p["S0"], p["K"]
+        _, b, mg = oracle_mod.price(B, S, K, p["r"], p["q"], p["sigma"], p["expiry"], T,
+                                    boundary=True, margin=True)
+        G, _ = pins.grid_binomial(S, K, p["r"], p["q"], p["sigma"], p["expiry"], T)
+        _, u, _, pp, m = pins.bopm_params(p["r"], p["q"], p["sigma"], p["expiry"], T)
+        for i in range(T):
+            j = np.arange(i + 1)
+            c = m * (1 - pp) * G[i + 1, :i + 1] + m * pp * G[i + 1, 1:i + 2]
+            gap = (c - (S * u ** (2.0 * j - i) - K)) / K
+            last = int(b[i])
+            if last >= 0:
+                assert abs(mg[2 * i] - gap[last]) <= 1e-12, (i, mg[2 * i], gap[last])
+            else:
+                assert np.isnan(mg[2 * i])
+            if last + 1 <= i:
+                assert abs(mg[2 * i + 1] + gap[last + 1]) <= 1e-12, (i, mg[2 * i + 1], -gap[last + 1])
+            else:
+                assert np.isnan(mg[2 * i + 1])
