@@ -77,6 +77,22 @@ def _lib():
     return _handle
 
 
+def european_sum(model: int, S: float, K: float, r: float, q: float, sigma: float, expiry: float, T: int,
+                 lib=None) -> float:
+    """European call on the binomial or trinomial lattice as a sum over the
+    binomial distribution of up moves (O(T); the trinomial lattice as 2T half
+    steps), the closed form of the linear stencil applied T times."""
+    lib = lib or _lib()
+    f = lib.aop_oracle_european_sum
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6 + [ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    out = ctypes.c_double(0.0)
+    rc = f(int(model), float(S), float(K), float(r), float(q), float(sigma), float(expiry), int(T), ctypes.byref(out))
+    if rc != 0:
+        raise OracleError("oracle rejected option: %s" % _STATUS.get(rc, rc))
+    return out.value
+
+
 def load_variant(so_path: str):
     """Load another build of the oracle source (used by the mutation tests)."""
     return _declare(ctypes.CDLL(so_path))

@@ -320,6 +320,81 @@ static int oracle_bsm_put(double S, double K, double r, double q, double sigma, 
 }
 
 /*
+ * European call on the binomial or trinomial lattice as a sum over the
+ * distribution of the number of up moves (the closed form of the linear
+ * stencil's T-fold application that the paper's European section evaluates
+ * with one FFT): price = disc * sum_k P(k) (S e^{(2k-n) h} - K)^+, with
+ * P(k) = C(n,k) p^k (1-p)^{n-k}.
+ *   binomial:  n = T, p of Fig. 1, h = a = V sqrt(dt), disc = m^T.
+ *   trinomial: a trinomial step with p_u = alpha^2, p_o = 2 alpha (1-alpha),
+ *              p_d = (1-alpha)^2 (Sec. 3) is two half steps of +-A/2 that go
+ *              up with probability alpha, so after T steps the position is
+ *              binomial over n = 2T half steps: p = alpha, h = A/2,
+ *              disc = m^T.
+ * P(k) is built from ratios of consecutive terms outward from the mode and
+ * normalised by its sum (no lgamma cancellation at large n).  O(n) work.
+ */
+static int european_sum(double S, double K, double p, double h, int64_t n, double disc, double *price)
+{
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    if (!w)
+        return OR_ENOMEM;
+    int64_t mode = (int64_t)floor((double)(n + 1) * p);
+    if (mode > n) mode = n;
+    if (mode < 0) mode = 0;
+    const double odds = p / (1.0 - p);
+    w[mode] = 1.0;
+    for (int64_t k = mode + 1; k <= n; ++k)
+        w[k] = w[k - 1] * ((double)(n - k + 1) / (double)k) * odds;
+    for (int64_t k = mode - 1; k >= 0; --k)
+        w[k] = w[k + 1] * ((double)(k + 1) / (double)(n - k)) / odds;
+    double z = 0.0, acc = 0.0;
+    for (int64_t k = 0; k <= n; ++k) {
+        z += w[k];
+        double pay = S * exp((double)(2 * k - n) * h) - K;
+        if (pay > 0.0 && isfinite(pay))
+            acc += w[k] * pay;
+        else if (pay > 0.0 && w[k] > 0.0)
+            acc = INFINITY;
+    }
+    free(w);
+    *price = disc * (acc / z);
+    return OR_OK;
+}
+
+int aop_oracle_european_sum(int model, double S, double K, double r, double q, double sigma, double E,
+                            int64_t T, double *price)
+{
+    if (!price)
+        return OR_EINVAL;
+    if (!(isfinite(S) && isfinite(K) && isfinite(r) && isfinite(q) && isfinite(sigma) &&
+          isfinite(E)) ||
+        S <= 0.0 || K <= 0.0 || sigma <= 0.0 || E <= 0.0 || T < 1 || q < 0.0)
+        return OR_EINVAL;
+    const double dt = E / (double)T;
+    const double m = exp(-r * dt);
+    const double disc = pow(m, (double)T);
+    if (model == OR_BINOMIAL) {
+        const double a = sigma * sqrt(dt);
+        const double u = exp(a), d = 1.0 / u;
+        const double p = (exp((r - q) * dt) - d) / (u - d);
+        if (!(p > 0.0 && p < 1.0))
+            return OR_EPROB;
+        return european_sum(S, K, p, a, T, disc, price);
+    }
+    if (model == OR_TRINOMIAL) {
+        const double A = sigma * sqrt(2.0 * dt);
+        const double su = exp(0.5 * A), sd = exp(-0.5 * A);
+        const double g = exp(0.5 * (r - q) * dt);
+        const double alpha = (g - sd) / (su - sd);
+        if (!(alpha > 0.0 && alpha < 1.0))
+            return OR_EPROB;
+        return european_sum(S, K, alpha, 0.5 * A, 2 * T, disc, price);
+    }
+    return OR_EINVAL;
+}
+
+/*
  * Entry point.  model: 0 binomial call, 1 trinomial call, 2 BSM put.
  * boundary: NULL or T+1 entries; margin: NULL or 2(T+1) entries.
  * lambda: dtau/ds^2 for the BSM grid (ignored otherwise).

@@ -9,6 +9,8 @@ drift term, the wrong tie rule) fails at least one of them.
 """
 import math
 
+import mpmath
+
 import numpy as np
 import pytest
 
@@ -458,3 +460,67 @@ def test_binomial_margins_against_full_numpy_grid(oracle_mod):
                 assert abs(mg[2 * i + 1] + gap[last + 1]) <= 1e-12, (i, mg[2 * i + 1], -gap[last + 1])
             else:
                 assert np.isnan(mg[2 * i + 1])
+
+
+def test_trinomial_negative_rate_breaks_step_bound(oracle_mod):
+    # Why the library rejects a trinomial call with R < 0: the decomposition
+    # needs the boundary to drop by at most two columns per row (the cone of a
+    # trinomial cell widens by two per row), which the lemmas of Sec. 3 give
+    # for R >= 0.  With R < 0 and Y = 0 the oracle shows drops of three or
+    # more; the binomial lattice keeps its one-column bound on the same inputs.
+    prm = (88.04753706433236, 121.32578641244521, -0.038748219583468815, 0.0, 0.4966706867960785,
+           1.5164334456388935)
+    T = 1000
+    _, b, _ = oracle_mod.price(TR, *prm, T, boundary=True)
+    drops = [int(b[i + 1] - b[i]) for i in range(T - 1) if b[i + 1] >= 0]
+    assert max(drops) > 2
+    _, b, _ = oracle_mod.price(B, *prm, T, boundary=True)
+    assert max(int(b[i + 1] - b[i]) for i in range(T - 1) if b[i + 1] >= 0) <= 1
+    # with R >= 0 and a dividend the trinomial bound holds on the same spot,
+    # strike and volatility (with Y = 0 and R >= 0 nothing exercises below the
+    # expiry row in exact arithmetic, and the library prices that case as one
+    # correlation without a boundary)
+    for r in (0.0, 0.02):
+        _, b, _ = oracle_mod.price(TR, prm[0], prm[1], r, 0.02, prm[4], prm[5], T, boundary=True)
+        assert max(int(b[i + 1] - b[i]) for i in range(T - 1) if b[i + 1] >= 0) <= 2
+
+
+# ------------------------------------------ European closed-form lattice sums
+@pytest.mark.parametrize("model", [B, TR])
+def test_european_sum_equals_lattice_induction(oracle_mod, model):
+    # The O(T) sum over the up-move distribution equals the plain induction
+    # without exercise (the linear stencil applied T times) for both lattices.
+    rng = np.random.default_rng([110, model])
+    for T in (1, 2, 3, 17, 256, 2048):
+        for _ in range(4):
+            p = inputs.draw_params(rng, model)
+            args = (p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T)
+            got = oracle_mod.european_sum(model, *args)
+            ref = oracle_mod.price(model, *args, american=False)
+            assert abs(got - ref) <= 1e-12 * max(ref, 1e-3 * p["K"]), (T, got, ref)
+
+
+@pytest.mark.parametrize("model", [B, TR])
+def test_european_sum_against_high_precision(oracle_mod, model):
+    # 40-digit binomial sums (trinomial: its own three-way path sum) at T where
+    # the recurrence runs a few thousand terms from the mode.
+    with mpmath.workdps(40):
+        for (S, K, r, q, s, E, T) in ((100.0, 95.0, 0.05, 0.02, 0.3, 1.2, 3000), (80.0, 120.0, 0.03, 0.01, 0.45, 2.0, 1500)):
+            got = oracle_mod.european_sum(model, S, K, r, q, s, E, T)
+            if model == B:
+                _, u, _, p, m = pins.bopm_params(r, q, s, E, T)
+                mp_ = mpmath.mpf
+                dt = mp_(E) / T
+                a = mp_(s) * mpmath.sqrt(dt)
+                uu = mpmath.e ** a
+                pp = (mpmath.e ** ((mp_(r) - q) * dt) - 1 / uu) / (uu - 1 / uu)
+                tot = mp_(0)
+                for k in range(T + 1):
+                    x = S * mpmath.e ** ((2 * k - T) * a)
+                    if x > K:
+                        tot += mpmath.binomial(T, k) * pp ** k * (1 - pp) ** (T - k) * (x - K)
+                exact = tot * mpmath.e ** (-mp_(r) * E)
+            else:
+                exact = pins.mp_trinomial(S, K, r, q, s, E, min(T, 400), american=False)
+                got = oracle_mod.european_sum(model, S, K, r, q, s, E, min(T, 400))
+            assert abs(got - float(exact)) <= 1e-12 * float(exact), (got, exact)
