@@ -55,9 +55,11 @@ typedef enum {
 typedef enum {
     AOP_OK = 0,
     AOP_EINVAL = 1,    /* non-finite or non-positive S, K, V, E; T < 1; unknown model;
-                          Y != 0 for the BSM put; bad lambda */
-    AOP_EPROB = 2,     /* lattice probability outside (0,1) or a BSM scheme
-                          coefficient negative (explicit-scheme stability) */
+                          Y != 0 for the BSM put; bad lambda; unknown flag bits */
+    AOP_EPROB = 2,     /* lattice probability outside (0,1), a BSM scheme
+                          coefficient negative (explicit-scheme stability), or
+                          an American trinomial call with R < 0 (outside the
+                          hypotheses of the boundary lemmas of Sec. 3) */
     AOP_ENOMEM = 3,    /* workspace too small / allocation failed */
     AOP_EDEVICE = 4,   /* HIP runtime error */
     AOP_ETOOBIG = 5,   /* T above AOP_MAX_T */
@@ -67,7 +69,15 @@ typedef enum {
 
 #define AOP_MAX_T (1LL << 21)
 
-/* One option (host memory).  flags: reserved, must be 0. */
+/* Option flags.  AOP_EUROPEAN: exercise at expiry only.  The method then
+ * needs no boundary search: the root is one FFT correlation of the expiry
+ * row (lattices: row T-1, computed directly from it) with the multi-step
+ * stencil kernel, as in the paper's section on the European call under the
+ * binomial model; boundary outputs hold -1 (lattices) or INT64_MIN (BSM)
+ * below the expiry row, whose own entry is still reported. */
+#define AOP_EUROPEAN 1
+
+/* One option (host memory).  flags: 0 (American) or AOP_EUROPEAN. */
 typedef struct {
     int32_t model;   /* aop_model */
     int32_t flags;

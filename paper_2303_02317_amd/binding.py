@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libaop.so")
 
 AOP_BINOMIAL_CALL, AOP_TRINOMIAL_CALL, AOP_BSM_PUT = 0, 1, 2
 AOP_FP64, AOP_MIXED = 0, 1
+AOP_EUROPEAN = 1  # aop_option.flags bit: exercise at expiry only
 STATUS = {0: "ok", 1: "EINVAL", 2: "EPROB", 3: "ENOMEM", 4: "EDEVICE", 5: "ETOOBIG", 6: "ECANCELED",
           7: "ENOTIMPL"}
 BSM_NONE = np.iinfo(np.int64).min
@@ -127,7 +128,8 @@ def _check(rc, what):
 def options_array(opts) -> ctypes.Array:
     arr = (AopOption * max(1, len(opts)))()
     for i, o in enumerate(opts):
-        arr[i] = AopOption(int(o["model"]), 0, float(o["S0"]), float(o["K"]), float(o["r"]), float(o["q"]),
+        flags = AOP_EUROPEAN if o.get("european", False) else 0
+        arr[i] = AopOption(int(o["model"]), flags, float(o["S0"]), float(o["K"]), float(o["r"]), float(o["q"]),
                            float(o["sigma"]), float(o["expiry"]), int(o["T"]))
     return arr
 

@@ -37,8 +37,10 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
     if (!(std::isfinite(o.S0) && std::isfinite(o.K) && std::isfinite(o.r) && std::isfinite(o.q) &&
           std::isfinite(o.sigma) && std::isfinite(o.expiry)))
         return AOP_EINVAL;
-    if (o.S0 <= 0 || o.K <= 0 || o.sigma <= 0 || o.expiry <= 0 || o.q < 0 || o.T < 1 || o.flags != 0)
+    if (o.S0 <= 0 || o.K <= 0 || o.sigma <= 0 || o.expiry <= 0 || o.q < 0 || o.T < 1 ||
+        (o.flags & ~AOP_EUROPEAN) != 0)
         return AOP_EINVAL;
+    const bool european = (o.flags & AOP_EUROPEAN) != 0;
     if (o.T > AOP_MAX_T) return AOP_ETOOBIG;
     const double T = (double)o.T;
     d.T = o.T;
@@ -76,6 +78,13 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         const double po = 1.0 - pu - pd;
         const double m = std::exp(-o.r * dt);
         if (!(pu > 0.0 && pd > 0.0 && po >= 0.0)) return AOP_EPROB;
+        // The trinomial boundary lemmas of Sec. 3 (the boundary drops by at
+        // most two columns per row, so a trapezoid's left part is all
+        // continuation) are shown for a non-negative risk-free rate.  With
+        // R < 0 and no dividend a row's top cell can exercise under an
+        // all-continuation row, a drop of three or more columns, so the
+        // decomposition does not apply.
+        if (o.r < 0.0 && !european) return AOP_EPROB;
         d.a = A;
         d.no_green = (o.q == 0.0 && o.r >= 0.0);  // as for the binomial lattice
         d.w0 = m * pd;
@@ -106,6 +115,7 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         return AOP_EINVAL;
     }
     d.model = o.model;
+    d.european = european ? 1 : 0;
     return AOP_OK;
 }
 

@@ -32,7 +32,8 @@ struct Desc {
     int64_t arena_len;  // doubles in the recursion arena
     int64_t nfft;       // complex elements in the FFT scratch
     int64_t out_index;  // index of this option in the caller's arrays
-    int64_t no_green;   // lattice call with Y = 0: no exercise cell below the expiry row (Lemma 2.3)
+    int32_t no_green;   // lattice call with Y = 0, R >= 0: no exercise cell below the expiry row (Lemma 2.3)
+    int32_t european;   // exercise only at expiry: the root is one correlation of the expiry row
     int64_t scr_len;    // complex elements of FFT scratch (a stack shared by the outstanding correlations)
 };
 static_assert(sizeof(Desc) == 128, "descriptor is 128 bytes");

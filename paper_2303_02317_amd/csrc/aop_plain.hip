@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__rest
             for (int c = 0; c < PL_C; ++c) {
                 x[c] *= u;  // S u^{col - i} one row lower
                 const double e = x[c] - d.K;
-                g[c] = pl_red(nx[c], e) ? nx[c] : e;
+                g[c] = (d.european || pl_red(nx[c], e)) ? nx[c] : e;
             }
         }
         const ll iout = itop - r;
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__rest
             for (int c = 1; c < PL_C - 1; ++c) nx[c] = d.w0 * g[c - 1] + d.w1 * g[c] + d.w2 * g[c + 1];
             nx[PL_C - 1] = d.w0 * g[PL_C - 2] + d.w1 * g[PL_C - 1] + d.w2 * nv;
 #pragma unroll
-            for (int c = 0; c < PL_C; ++c) g[c] = (x[c] > nx[c]) ? x[c] : nx[c];
+            for (int c = 0; c < PL_C; ++c) g[c] = (!d.european && x[c] > nx[c]) ? x[c] : nx[c];
         }
         const ll hi_out = T - n - r;
         for (int c = 0; c < PL_C; ++c) {

@@ -41,8 +41,8 @@ typedef long long ll;
 
 // Model parameters, passed by value so that they live in registers.
 struct Mp {
-    int model;
-    ll T, no_green;
+    int model, no_green, european;
+    ll T;
     double S, K, a, s0, w0, w1, w2;
 };
 __device__ __forceinline__ Mp make_mp(const Desc &d)
@@ -51,6 +51,7 @@ __device__ __forceinline__ Mp make_mp(const Desc &d)
     p.model = d.model;
     p.T = d.T;
     p.no_green = d.no_green;
+    p.european = d.european;
     p.S = d.S;
     p.K = d.K;
     p.a = d.a;
@@ -1089,7 +1090,7 @@ __device__ __forceinline__ int resolve_block(unsigned mlo, unsigned mhi, int nb,
 // e <- u e + K(u-1); f1 (f2) is the exercise value of column c0+64 (c0+65) in
 // the row being read, the cells beyond the band that enter through the
 // shift's fill.  Returns whether the lane's new cell is red (continuation >=
-// exercise).
+// exercise, continuation finite).
 template <bool TRI>
 __device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, double &f2, double u, double ku, double w0,
                                          double w1, double w2)
@@ -1107,8 +1108,12 @@ __device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, doubl
         c = fma(w1, g1, w0 * g);
     }
     e = fma(e, u, ku);
-    g = vmax_f64(c, e);
-    return c >= e;
+    // Definition 2.1 with the non-finite guard: c >= e and c finite (then e
+    // is finite too).  A continuation value that overflowed marks an exercise
+    // cell, whose value is its exercise value.
+    const bool red = (c >= e) && (c < INFINITY);
+    g = red ? c : e;
+    return red;
 }
 
 // Rows i0-1 .. i0-h of a lattice (binomial: row i has columns 0..i, cell j
@@ -2490,7 +2495,7 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
                 c = d.w0 * g0 + d.w1 * g1 + d.w2 * g2;
             }
             const double e = bin ? ex_bin(d, T - 1, j) : ex_tri(d, T - 1, j);
-            const bool red = red_of(c, e);
+            const bool red = d.european || red_of(c, e);  // European: no exercise before expiry
             rowA[j] = red ? c : e;
             if (red) lastT1 = j;
         }
@@ -2500,28 +2505,30 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
     lastT1 = block_max(lastT1, red_sh);
     if (cx.bnd && tid == 0) {
         cx.bnd[T] = lastT;
-        cx.bnd[T - 1] = lastT1;
+        cx.bnd[T - 1] = d.european ? -1 : lastT1;
     }
     if (tid == 0) cx.st->cyc_rows += clk() - tr0;
     ll i0 = T - 1, b = lastT1;
     double *src = rowA, *dst = rowB;
-    if (T > 1 && (d.no_green || b == wT - (bin ? 1 : 2))) {
+    if (T > 1 && (d.no_green || d.european || b == wT - (bin ? 1 : 2))) {
         // No exercise cell below the expiry row: with Y = 0 Lemma 2.3 leaves
         // none (the classification of far in-the-money cells of row T-1 is
         // then rounding noise), and an entirely red row T-1 keeps every row
         // below red (Corollary 2.6: the boundary drops at most one cell per
         // row while the row shrinks by one or two).  The root is then one
         // linear functional of row T-1, whose values grow like S u^{col}, so
-        // the correlation is tilted about the at-the-money column tc.
+        // the correlation is tilted about the at-the-money column tc.  A
+        // European option (exercise at expiry only) takes the same single
+        // correlation: row T-1 was computed without exercise.
         b = wT - (bin ? 1 : 2);
-        if (cx.bnd && tid == 0) cx.bnd[T - 1] = b;
+        if (cx.bnd && tid == 0) cx.bnd[T - 1] = d.european ? -1 : b;
         const double beta = bin ? 2.0 * d.a : d.a;
         double tc = bin ? 0.5 * ((double)(T - 1) + log(d.K / d.S) / d.a)
                         : (double)(T - 1) + log(d.K / d.S) / d.a;
         if (tc < 0.0) tc = 0.0;
         if (tc > (double)b) tc = (double)b;
         if (cx.bnd)
-            for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = bin ? i : 2 * i;
+            for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = d.european ? -1 : (bin ? i : 2 * i);
         const ll hh = T - 1;
         conv_submit<PREC>(cx, SLOT_TOP, 0, src, b + 1, hh, bin ? 0 : hh, 1, dst, beta, tc);
         conv_wait<PREC>(cx, SLOT_TOP);
@@ -2585,7 +2592,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
             const double gm = ex_bsm(d, k - 1), gp = ex_bsm(d, k + 1);
             const double cont = d.w0 * (gm > 0.0 ? gm : 0.0) + d.w1 * (g > 0.0 ? g : 0.0) +
                                  d.w2 * (gp > 0.0 ? gp : 0.0);
-            const bool green = g > cont;
+            const bool green = !d.european && g > cont;  // European: exercise at expiry only
             A[k] = green ? g : cont;
             if (green) f1 = k;
         }

@@ -52,6 +52,11 @@ def test_validation_model_specific():
     assert binding.validate(o) == 0
     # p > 1: the up move cannot cover the growth at T = 1
     assert binding.validate(dict(inputs.CONFIG1, r=0.9, q=0.0, sigma=0.01, T=1)) == 2
+    # a trinomial call with R < 0 is outside the hypotheses of the Sec. 3 lemmas;
+    # the binomial call and the BSM put accept it
+    assert binding.validate(dict(inputs.CONFIG1, model=1, r=-0.01, q=0.0)) == 2
+    assert binding.validate(dict(inputs.CONFIG1, model=0, r=-0.01, q=0.0)) == 0
+    assert binding.validate(dict(inputs.CONFIG1, model=2, r=-0.01, q=0.0)) == 0
 
 
 def test_workspace_bytes_grow_with_T():
