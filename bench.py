@@ -11,7 +11,16 @@ workload) through the C ABI.  Prints one JSON line:
                computed expiry-adjacent row) over its average launch time,
                against the 8 TB/s HBM3E peak; band_fp64 gives the band
                stencil's FP64 rate against the 78.6 TFLOP/s vector peak
-  accuracy     max error against stored oracle prices of the same options
+  accuracy     per-option error against stored oracle prices of the same
+               options; all_ok requires every checked option within the FP64
+               tolerance
+  plain_gpu    the plain Theta(T^2) GPU stencil on the same batch (one step)
+               and the FFT path's speed-up over it
+  extra        the other seeded workloads (trinomial mixed precision 2^20,
+               BSM 2^18 FP64 and mixed, European 2^20), each with its
+               throughput and per-option errors
+  serve        the serving mix: capacity, p50/p99 latency at 0.7 capacity,
+               and the served batches' algorithmic bytes against HBM peak
   cpu_baseline the CPU oracle (plain Theta(T^2) induction) on a bounded
                sample, one option per host thread
 
@@ -22,6 +31,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -80,13 +90,84 @@ def measured_traffic(workload: str):
         return None, "summary has no traffic figure"
 
 
-def golden_prices(model: int, log2T: int):
-    path = os.path.join(ROOT, "tests", "golden",
-                        "oracle_%s_c%d_t%d.json" % (GOLDEN_NAME[model], CONFIG_ID[model], log2T))
+def golden_prices(model: int, log2T: int, european: bool = False):
+    """Stored oracle prices of the seeded batch (tests/golden/make_golden.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_%s%s_c%d_t%d.json" % (
+        "european_" if european else "", GOLDEN_NAME[model], CONFIG_ID[model], log2T))
     if not os.path.exists(path):
         return None
     doc = json.load(open(path))
     return [r["price"] for r in doc["options"]]
+
+
+def accuracy_of(prices, ref, opts, mixed: bool = False):
+    """Errors against stored oracle prices (relative for prices >= 1e-3 K, absolute
+    in units of K below), with the per-option lists and the verdict against the
+    FP64 (1e-9 / 1e-13 K) or mixed-precision (1e-6 / 1e-9 K) tolerance."""
+    if ref is None:
+        return None
+    rel_tol, abs_tol = (1e-6, 1e-9) if mixed else (1e-9, 1e-13)
+    k = min(len(ref), len(opts))
+    big = [i for i in range(k) if abs(ref[i]) >= 1e-3 * opts[i]["K"]]
+    small = [i for i in range(k) if abs(ref[i]) < 1e-3 * opts[i]["K"]]
+    rel = [abs(prices[i] - ref[i]) / abs(ref[i]) for i in big]
+    ab = [abs(prices[i] - ref[i]) / opts[i]["K"] for i in small]
+    finite = all(math.isfinite(float(prices[i])) for i in range(k))
+    within = finite and all(r <= rel_tol for r in rel) and all(a <= abs_tol for a in ab)
+    return {"n_checked": k, "n_options": len(opts), "n_rel": len(big),
+            "max_rel_err": max(rel) if rel else None, "n_small": len(small),
+            "max_abs_err_over_K_small": max(ab) if ab else None,
+            "per_option_abs_err": [abs(float(prices[i]) - ref[i]) for i in range(k)],
+            "per_option_rel_err": [abs(float(prices[i]) - ref[i]) / max(abs(ref[i]), 1e-300) for i in range(k)],
+            "tolerance": {"rel": rel_tol, "abs_over_K": abs_tol},
+            "within_tolerance": within, "reference": "CPU oracle (FP64), stored"}
+
+
+def timed_batch(ctx, opts, precision, steps, warmup):
+    """Warm up, then time `steps` launches of one batch with HIP events on its stream."""
+    import torch
+
+    from paper_2303_02317_amd import binding
+
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(binding.workspace_bytes(opts, precision), dtype=torch.uint8, device="cuda")
+    L = None
+    for _ in range(warmup):
+        L = binding.launch_batch(ctx, opts, precision=precision, workspace=ws)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        evs[k][0].record(stream)
+        L = binding.launch_batch(ctx, opts, precision=precision, workspace=ws)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return L, wall, [a.elapsed_time(b) for a, b in evs]
+
+
+def extra_leg(ctx, name, model, log2T, precision, european=False, steps=2, warmup=1, n=64):
+    """One more seeded workload: throughput and per-option error against stored oracle prices."""
+    import numpy as np
+
+    from paper_2303_02317_amd import autotune, binding, inputs
+
+    opts = inputs.batch(CONFIG_ID[model], log2T, n, model)
+    if european:
+        opts = [dict(o, european=True) for o in opts]
+    autotune.apply(ctx, model, 1 << log2T, precision)
+    log("%s: %s T=2^%d %d options %s%s" % (name, GOLDEN_NAME[model], log2T, n, "mixed" if precision else "fp64",
+                                          " european" if european else ""))
+    L, wall, ms = timed_batch(ctx, opts, precision, steps, warmup)
+    prices = L.price.cpu().numpy()
+    cells = sum(float(o["T"]) ** 2 for o in opts)
+    acc = accuracy_of(prices, golden_prices(model, log2T, european), opts, mixed=precision == 1)
+    ok = bool(np.all(L.status == 0) and np.all(np.isfinite(prices))) and (acc is None or acc["within_tolerance"])
+    return {"workload": "%s American %s%s, T=2^%d, %d seeded options, %s" % (
+                GOLDEN_NAME[model], "put" if model == 2 else "call", " (European exercise)" if european else "",
+                log2T, n, "split-FP32 correlations, FP64 band/boundary/root" if precision else "FP64"),
+            "value": cells * steps / wall, "unit": "cells/s", "ms_per_step": wall / steps * 1e3,
+            "launch_ms": ms, "precision": "mixed" if precision else "fp64", "accuracy": acc, "all_ok": ok}
 
 
 def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
@@ -94,6 +175,7 @@ def cpu_baseline(opts_full, model, log2T, budget_s=20.0):
     import oracle
     from paper_2303_02317_amd import inputs
 
+    # the GPU machine gives one GPU a share of 16 host cores, whatever the machine reports
     cores = min(len(os.sched_getaffinity(0)), 16)
     # Sample: the first options of the same seeded batch, at a T whose Theta(T^2)
     # oracle cost per option is a few seconds (the oracle's T^2/s rate does not
@@ -180,6 +262,11 @@ def serve_bench(ctx, n_req: int, load: float = 0.7, max_inflight: int = 4, max_b
                           "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
                           "queue_p50_ms": 1e3 * float(np.percentile(que, 50)),
                           "batches": st_open["batches"], "peak_hbm_bytes": st_open["peak_bytes"]},
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "achieved": st_closed["alg_bytes"] / wall / 1e9,
+                         "frac": st_closed["alg_bytes"] / wall / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes": st_closed["alg_bytes"],
+                         "note": "closed loop: algorithmic bytes of the served batches over the wall time"},
             "config": dict({k: v for k, v in cfg.items() if k != "tunings"}, precision="fp64",
                            tuned_classes=len(cfg["tunings"])),
             "all_ok": ok, "same_prices_both_runs": same}
@@ -198,8 +285,10 @@ def main():
                     help="requests of the serving mix timed after the batch (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer twice (reference kernel for HBM byte counters)")
-    ap.add_argument("--plain", action="store_true",
-                    help="also time the plain Theta(T^2) GPU stencil on the same batch (one step)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip timing the plain Theta(T^2) GPU stencil on the same batch (one step)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (trinomial mixed 2^20, BSM 2^18 FP64 and mixed, European 2^20)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -262,23 +351,11 @@ def main():
     avg_s = float(np.mean(launch_ms)) / 1e3
     achieved = alg_bytes / avg_s / 1e9
 
-    ref = golden_prices(model, args.log2T)
-    accuracy = None
-    if ref is not None:
-        # Relative error is reported for prices >= 1e-3 K; below that the FFT's
-        # normwise error makes it meaningless, and the absolute error in units
-        # of K is reported instead (tolerances 1e-9 relative / 1e-13 K for FP64).
-        k = min(len(ref), n)
-        big = [i for i in range(k) if abs(ref[i]) >= 1e-3 * opts[i]["K"]]
-        small = [i for i in range(k) if abs(ref[i]) < 1e-3 * opts[i]["K"]]
-        rel = [abs(prices[i] - ref[i]) / abs(ref[i]) for i in big]
-        ab = [abs(prices[i] - ref[i]) / opts[i]["K"] for i in small]
-        within = all(r <= 1e-9 for r in rel) and all(a <= 1e-13 for a in ab)
-        accuracy = {"n_checked": k, "n_rel": len(big), "max_rel_err": max(rel) if rel else None,
-                    "n_small": len(small), "max_abs_err_over_K_small": max(ab) if ab else None,
-                    "within_fp64_tolerance": within,
-                    "reference": "CPU oracle (FP64 plain induction), stored"}
-    ok = bool(np.all(status == 0) and np.all(np.isfinite(prices)))
+    # Relative error is reported for prices >= 1e-3 K; below that the FFT's
+    # normwise error makes it meaningless, and the absolute error in units of
+    # K is reported instead (tolerances 1e-9 relative / 1e-13 K for FP64).
+    accuracy = accuracy_of(prices, golden_prices(model, args.log2T), opts)
+    ok = bool(np.all(status == 0) and np.all(np.isfinite(prices))) and bool(accuracy and accuracy["within_tolerance"])
     workload = "%s American %s, FFT nonlinear stencil, T=2^%d, %d seeded options" % (
         args.option_type, "put" if model == 2 else "call", args.log2T, n)
     traffic, traffic_src = measured_traffic(workload)
@@ -317,7 +394,7 @@ def main():
     busy = pool["helper_busy"] + pool["helper_idle"]
     line["pool"] = dict(pool, helper_busy_frac=(pool["helper_busy"] / busy) if busy else None,
                         tuning=ctx.tuning())
-    if args.plain:
+    if not args.no_plain:
         log("plain O(T^2) GPU stencil on the same batch ...")
         wsp = torch.empty(binding.plain_workspace_bytes(opts), dtype=torch.uint8, device="cuda")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -332,6 +409,15 @@ def main():
         agree = float(np.max(np.abs(pp - prices) / np.maximum(np.abs(pp), 1e-3 * np.array([o["K"] for o in opts]))))
         line["plain_gpu"] = {"value": cells / pw, "unit": "cells/s", "ms": pw * 1e3, "event_ms": e0.elapsed_time(e1),
                              "speedup_fft_vs_plain": pw / (wall / args.steps), "max_rel_diff_vs_fft": agree}
+    if not args.no_extra:
+        line["extra"] = {
+            "trinomial_mixed_T2p20": extra_leg(ctx, "config 3", 1, 20, 1),
+            "bsm_fp64_T2p18": extra_leg(ctx, "config 4", 2, 18, 0),
+            "bsm_mixed_T2p18": extra_leg(ctx, "config 4", 2, 18, 1),
+            "binomial_european_T2p20": extra_leg(ctx, "European", 0, 20, 0, european=True),
+            "trinomial_european_T2p20": extra_leg(ctx, "European", 1, 20, 0, european=True),
+        }
+        autotune.apply(ctx, model, 1 << args.log2T, 0)
     if args.serve_requests > 0:
         log("serving mix ...")
         line["serve"] = serve_bench(ctx, args.serve_requests)

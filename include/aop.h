@@ -21,9 +21,9 @@
  *
  * Conventions
  *   - Pointers named d_* are device (HBM) pointers; h_* are host pointers.
- *   - Nothing here allocates device memory except aop_ctx_create (twiddle
- *     table) and the synchronous helper aop_price; batch calls use the
- *     caller's workspace of at least aop_workspace_bytes() bytes.
+ *   - Nothing here allocates device memory except the synchronous helper
+ *     aop_price: the twiddle table, batch workspaces and the serving arena
+ *     are the caller's (e.g. torch tensors).
  *   - All functions return an aop_status; nothing throws across the ABI.
  *   - A context is not thread-safe: use one context per host thread.
  *   - Ties between continuation and exercise value count as continuation
@@ -92,25 +92,47 @@ typedef struct {
 
 typedef struct aop_ctx aop_ctx;
 
-/* Create a context on HIP device `device`: allocates and fills the FFT
- * twiddle table (about 64 MB) and a pinned staging buffer.  The context
- * owns these until aop_ctx_destroy.  lambda = dtau/ds^2 of the BSM grid
- * (pass 0 for the default 1/3). */
-aop_status aop_ctx_create(int device, double lambda, aop_ctx **out);
+/* Bytes of the FFT twiddle table a context needs (e^{-2 pi i t / 2^22},
+ * t < 2^22, complex FP64: 64 MiB).  Used by the correlations of Sec. 2.3
+ * ("Solving a trapezoid": each h-step kernel application is an FFT
+ * correlation). */
+size_t aop_twiddle_bytes(void);
+
+/* Create a context on HIP device `device`.
+ *   lambda      dtau/ds^2 of the BSM grid (Sec. 4.2, eq. bsmG; 0: the default
+ *               1/3, at most 1/2 so that the scheme's coefficients stay >= 0).
+ *   d_twiddles  device buffer of tw_bytes >= aop_twiddle_bytes(), 16-byte
+ *               aligned, owned by the caller (e.g. a torch tensor); the context
+ *               fills it (synchronously) and reads it until aop_ctx_destroy,
+ *               which does not free it.
+ * The context allocates no device memory; it holds a pinned host staging
+ * buffer for descriptors.  Errors: AOP_EINVAL (bad lambda, NULL or misaligned
+ * table), AOP_ENOMEM (table too small), AOP_EDEVICE. */
+aop_status aop_ctx_create(int device, double lambda, void *d_twiddles, size_t tw_bytes, aop_ctx **out);
+/* Release the context (not the caller's twiddle table). */
 aop_status aop_ctx_destroy(aop_ctx *ctx);
 
-/* Bytes of device workspace a batch of n options needs (host options).
+/* Bytes of device workspace a batch of n options needs (host options): per
+ * option two row buffers of the lattice (Fig. 1: row i of the binomial lattice
+ * has i+1 cells; Sec. 3: 2i+1 trinomial cells; Sec. 4.2: the 2T+1-point BSM
+ * cone), the recursion's middle rows (Sec. 2.3, "Solving a trapezoid") and
+ * the FFT scratch, plus the batch's descriptors, counters and work pool.
  * Invalid options contribute nothing; their status is reported by the
  * pricing call. */
 aop_status aop_workspace_bytes(const aop_option *h_opts, int64_t n, int32_t precision,
                                size_t *bytes);
 
-/* Validate one option and report its status without pricing it. */
+/* Validate one option and report its status without pricing it: the
+ * parameter checks of Fig. 1 (binomial p in (0,1)), Sec. 3 (trinomial
+ * probabilities) and eq. bsmG (BSM coefficients >= 0); see aop_status. */
 aop_status aop_validate(const aop_option *h_opt, double lambda);
 
 /*
- * Price n options with the FFT nonlinear-stencil method, asynchronously on
- * `hip_stream` (a hipStream_t; NULL = default stream).
+ * Price n options with the FFT nonlinear-stencil method (Sec. 2.3 for the
+ * binomial call: "Partitioning the triangle" into trapezoids and "Solving a
+ * trapezoid" recursively; Sec. 3 for the trinomial call; Sec. 4.3 for the BSM
+ * put), asynchronously on `hip_stream` (a hipStream_t; NULL = default stream).
+ * The price is the root value G[0][0] of Def. 2.1 (BSM: K v^T_0).
  *   h_opts      host array of n options (read before return).
  *   d_workspace device buffer of ws_bytes >= aop_workspace_bytes(); must stay
  *               alive and untouched until the stream reaches this work.
@@ -134,7 +156,8 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *h_opts, int64_t n, in
                            void *hip_stream);
 
 /*
- * Graph form of aop_price_batch: the batch's launch (clearing of the work
+ * Graph form of aop_price_batch (same method and outputs; the launch form is
+ * this library's, the paper runs on CPU cores): the batch's launch (clearing of the work
  * pool and the persistent solve kernel) is captured once in a hipGraph and
  * replayed with aop_graph_launch, for callers that price the same batch of
  * options repeatedly.  Arguments as in aop_price_batch (the graph uses the
@@ -152,16 +175,24 @@ aop_status aop_graph_launch(aop_graph *graph, void *hip_stream);
 aop_status aop_graph_destroy(aop_graph *graph);
 
 /*
- * Comparison path: the plain Theta(T^2) backward induction of Fig. 1 on the
- * GPU (same arguments and semantics as aop_price_batch, FP64 only; the
- * boundary is not reported: pass NULL).  Workspace: aop_plain_workspace_bytes.
+ * Comparison path: the plain Theta(T^2) backward induction of Fig. 1 (the
+ * standard looping code; Table 2's Theta(T^2) work) on the GPU, every cell
+ * updated with the direct max(continuation, exercise) stencil of Def. 2.1
+ * (Sec. 3 trinomial, eq. bsmG for BSM).  Same arguments and semantics as
+ * aop_price_batch, FP64 only (precision is not taken).  d_boundary: NULL or
+ * n * boundary_stride int64 (boundary_stride >= max T + 1), the same
+ * per-row boundary as aop_price_batch reports, found by scanning every cell.
+ * Workspace: aop_plain_workspace_bytes (two row buffers per option).
  */
 aop_status aop_plain_workspace_bytes(const aop_option *h_opts, int64_t n, size_t *bytes);
 aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *h_opts, int64_t n,
                                  void *d_workspace, size_t ws_bytes, double *d_price,
-                                 int32_t *h_status, void *hip_stream);
+                                 int32_t *h_status, int64_t *d_boundary, int64_t boundary_stride,
+                                 void *hip_stream);
 
-/* Work an option's solve performed (written by the kernel into the workspace). */
+/* Work an option's solve performed (written by the kernel into the workspace):
+ * the correlations of Sec. 2.3 (two per trapezoid), the band rows of its base
+ * case, and clock counters of where the driver spent its time. */
 typedef struct {
     int64_t convs;        /* FFT correlations (h-step kernel applications) */
     int64_t conv_in;      /* sum of input lengths (doubles read from HBM) */
@@ -183,17 +214,21 @@ typedef struct {
 
 /* Copy the work counters of the last aop_price_batch on this workspace to the
  * host (synchronous; call after the stream has passed the batch).  h_stats:
- * n entries; entries of rejected options are zero. */
+ * n entries in the caller's order; entries of rejected options are zero.
+ * These counters give the algorithmic HBM bytes of the correlations (Sec. 2.3:
+ * each reads its input segment and writes its output segment once). */
 aop_status aop_batch_stats(const void *d_workspace, int64_t n, aop_stats *h_stats);
 
-/* Device-side error code of each option of the last aop_price_batch (or graph
+/* Device-side error code (this library's geometry and deadline checks, not a
+ * quantity of the paper) of each option of the last aop_price_batch (or graph
  * replay) on this workspace, in the caller's order (synchronous): 0 none,
  * 1 a range check failed, 2 recursion stack, 3 arena or FFT scratch exhausted,
  * 5 a wait passed its deadline, 6 priced after the launch aborted.  An option
  * with a nonzero code has a NaN price. */
 aop_status aop_batch_errors(const void *d_workspace, int64_t n, int32_t *h_err);
 
-/* Work-pool counters of the last aop_price_batch on this workspace
+/* Work-pool counters (the pool runs the independent correlations of a
+ * trapezoid, Sec. 2.3, on idle workgroups) of the last aop_price_batch on this workspace
  * (synchronous): h_out[0] workgroups, [1] tiles computed by helper
  * workgroups, [2] helper busy cycles, [3] helper idle cycles, [4] options
  * finished, [5] 1 if the launch aborted (a wait passed its deadline or a job was refused), [6..7] 0. */
@@ -232,7 +267,12 @@ aop_status aop_ctx_set_tuning(aop_ctx *ctx, const aop_tuning *tuning);
  * Serving: continuous batching of pricing requests of mixed model and T,
  * priced by the persistent FFT-path kernel while new requests keep arriving.
  *
- * A server owns a device arena of hbm_budget bytes (its HBM budget) and a
+ * (The paper prices one option at a time; serving is this library's form of
+ * the same method for request streams: each request is priced exactly as by
+ * aop_price_batch, Sec. 2.3 / 3 / 4.3.)
+ *
+ * A server uses a device arena of hbm_budget bytes that the caller owns (its
+ * HBM budget) and a
  * scheduler thread with max_inflight launch slots, each with its own HIP
  * stream and 1/max_inflight of the compute units.  When a slot is free the
  * scheduler takes the oldest pending request, adds younger requests of the same
@@ -260,7 +300,7 @@ typedef struct {
 } aop_class_tuning;
 
 typedef struct {
-    size_t hbm_budget;    /* device bytes for workspaces (0: a quarter of the free memory) */
+    size_t hbm_budget;    /* bytes of d_arena the server may use for workspaces */
     int32_t max_inflight; /* batches on the device at once, 1..16 */
     int32_t max_batch;    /* options per batch, 1..4096 */
     int32_t precision;    /* AOP_FP64 or AOP_MIXED, for every request */
@@ -269,6 +309,8 @@ typedef struct {
                                         a batch uses the entry of its model and precision nearest
                                         in log2T, else the context's tuning */
     int64_t n_tunings;
+    void *d_arena;        /* device buffer of hbm_budget bytes, 256-byte aligned, owned by the
+                             caller (e.g. a torch tensor); must outlive the server */
 } aop_server_config;
 
 typedef struct {
@@ -281,6 +323,9 @@ typedef struct {
     double latency_s;    /* seconds from submission to the result being available on the host */
 } aop_result;
 
+/* Start a server on the caller's arena (allocates no device memory: streams,
+ * events and pinned host buffers only).  AOP_EINVAL for a bad configuration or
+ * a NULL / misaligned arena. */
 aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_server **out);
 /* Queue n requests (host arrays, copied before return); arrival time is now. */
 aop_status aop_server_submit(aop_server *server, const aop_option *h_opts, const uint64_t *h_ids, int64_t n);
@@ -289,19 +334,24 @@ aop_status aop_server_submit(aop_server *server, const aop_option *h_opts, const
  * server's error state (AOP_OK while healthy). */
 aop_status aop_server_poll(aop_server *server, aop_result *h_out, int64_t max, int64_t *n_out, int32_t wait_us);
 /* h_out[0] submitted, [1] completed, [2] batches launched, [3] batches in flight,
- * [4] requests pending, [5] peak arena bytes in use, [6] arena bytes, [7] workgroups per batch. */
-aop_status aop_server_stats(aop_server *server, int64_t h_out[8]);
+ * [4] requests pending, [5] peak arena bytes in use, [6] arena bytes, [7] workgroups per batch,
+ * [8] algorithmic HBM bytes of the finished batches (8 bytes per correlation input and output
+ * cell and per directly computed cell, as aop_stats counts them). */
+aop_status aop_server_stats(aop_server *server, int64_t h_out[9]);
 /* Finish every queued request, then release the server's device memory and streams. */
 aop_status aop_server_destroy(aop_server *server);
 
-/* Synchronous convenience: price one option, allocating and freeing its own
- * workspace.  h_boundary: NULL or a host array of T+1 int64. */
+/* Synchronous convenience: price one option as aop_price_batch does (Sec. 2.3
+ * / 3 / 4.3), allocating and freeing its own device workspace -- the one entry
+ * point that allocates device memory.  h_boundary: NULL or a host array of
+ * T+1 int64. */
 aop_status aop_price(aop_ctx *ctx, const aop_option *h_opt, int32_t precision, double *h_price,
                      int64_t *h_boundary);
 
-/* Wait for all work on hip_stream. */
+/* Wait for all work on hip_stream (plumbing, no quantity of the paper). */
 aop_status aop_sync(void *hip_stream);
 
+/* Text of a status code (plumbing). */
 const char *aop_status_str(aop_status s);
 
 /* Library version string. */

@@ -24,7 +24,7 @@ STATUS = {0: "ok", 1: "EINVAL", 2: "EPROB", 3: "ENOMEM", 4: "EDEVICE", 5: "ETOOB
 BSM_NONE = np.iinfo(np.int64).min
 
 #: Every symbol include/aop.h declares.
-EXPORTS = ["aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
+EXPORTS = ["aop_twiddle_bytes", "aop_ctx_create", "aop_ctx_destroy", "aop_workspace_bytes", "aop_validate", "aop_price_batch",
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
            "aop_status_str", "aop_version", "aop_pool_stats", "aop_pool_abort_info", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
            "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
@@ -55,7 +55,8 @@ class AopClassTuning(ctypes.Structure):
 class AopServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("tunings", ctypes.POINTER(AopClassTuning)), ("n_tunings", ctypes.c_int64)]
+                ("tunings", ctypes.POINTER(AopClassTuning)), ("n_tunings", ctypes.c_int64),
+                ("d_arena", ctypes.c_void_p)]
 
 
 class AopResult(ctypes.Structure):
@@ -64,7 +65,7 @@ class AopResult(ctypes.Structure):
 
 
 SERVER_STATS = ["submitted", "completed", "batches", "inflight", "pending", "peak_bytes", "arena_bytes",
-                "workgroups_per_batch"]
+                "workgroups_per_batch", "alg_bytes"]
 
 
 class AopOption(ctypes.Structure):
@@ -86,13 +87,14 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     sig = {
-        "aop_ctx_create": (I32, [ctypes.c_int, D, ctypes.POINTER(P)]),
+        "aop_twiddle_bytes": (SZ, []),
+        "aop_ctx_create": (I32, [ctypes.c_int, D, P, SZ, ctypes.POINTER(P)]),
         "aop_ctx_destroy": (I32, [P]),
         "aop_workspace_bytes": (I32, [P, I64, I32, ctypes.POINTER(SZ)]),
         "aop_validate": (I32, [P, D]),
         "aop_price_batch": (I32, [P, P, I64, I32, P, SZ, P, P, P, I64, P]),
         "aop_plain_workspace_bytes": (I32, [P, I64, ctypes.POINTER(SZ)]),
-        "aop_price_batch_plain": (I32, [P, P, I64, P, SZ, P, P, P]),
+        "aop_price_batch_plain": (I32, [P, P, I64, P, SZ, P, P, P, I64, P]),
         "aop_batch_stats": (I32, [P, I64, P]),
         "aop_price": (I32, [P, P, I32, ctypes.POINTER(D), P]),
         "aop_sync": (I32, [P]),
@@ -142,7 +144,9 @@ def _stream_handle(stream):
 
 
 class Context:
-    """An aop_ctx on one device (owns the twiddle table and a pinned staging buffer)."""
+    """An aop_ctx on one device.  The twiddle table is a torch tensor held here
+    (the library fills and reads it); the context itself keeps a pinned
+    staging buffer."""
 
     def __init__(self, device: int = 0, lam: float = 1.0 / 3.0):
         # PyTorch owns device memory and streams: bring its HIP state up
@@ -151,8 +155,11 @@ class Context:
 
         torch.cuda.init()
         lib = load()
+        nb = int(lib.aop_twiddle_bytes())
+        self.twiddles = torch.empty(nb, dtype=torch.uint8, device=torch.device("cuda", device))
         self._h = ctypes.c_void_p()
-        _check(lib.aop_ctx_create(int(device), float(lam), ctypes.byref(self._h)), "aop_ctx_create")
+        _check(lib.aop_ctx_create(int(device), float(lam), ctypes.c_void_p(self.twiddles.data_ptr()), nb,
+                                  ctypes.byref(self._h)), "aop_ctx_create")
         self.device = device
         self.lam = lam
 
@@ -179,6 +186,7 @@ class Context:
         if self._h:
             load().aop_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self.twiddles = None
 
     def __del__(self):
         try:
@@ -249,7 +257,7 @@ def price_batch(ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = 
     return L.price.cpu().numpy(), L.status.copy(), b
 
 
-def launch_plain(ctx: Context, opts, stream=None, workspace=None):
+def launch_plain(ctx: Context, opts, stream=None, workspace=None, boundary: bool = False):
     """Enqueue the plain Theta(T^2) GPU stencil on ``opts`` (comparison path)."""
     import torch
 
@@ -262,11 +270,14 @@ def launch_plain(ctx: Context, opts, stream=None, workspace=None):
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     status = np.zeros(max(n, 1), dtype=np.int32)
+    stride = max(int(o["T"]) for o in opts) + 1 if (boundary and n) else 0
+    bnd = torch.empty((max(n, 1), max(stride, 1)), dtype=torch.int64, device=dev) if boundary else None
     rc = lib.aop_price_batch_plain(ctx.handle, arr, n, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    ctypes.c_void_p(price.data_ptr()), status.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_void_p(bnd.data_ptr()) if bnd is not None else None, stride,
                                    _stream_handle(stream))
     _check(rc, "aop_price_batch_plain")
-    return Launch(price[:n], status[:n], None, workspace)
+    return Launch(price[:n], status[:n], bnd[:n] if bnd is not None else None, workspace)
 
 
 def batch_stats(launch: "Launch", n: int) -> np.ndarray:
@@ -320,8 +331,18 @@ class Server:
 
     def __init__(self, ctx: Context, hbm_budget: int = 0, max_inflight: int = 4, max_batch: int = 64,
                  precision: int = AOP_FP64, tunings=None):
-        """tunings: [(model, log2T, precision, schedule dict)] per size class (the autotuner's table)."""
+        """tunings: [(model, log2T, precision, schedule dict)] per size class (the autotuner's table).
+        hbm_budget: bytes of the arena this object allocates as a torch tensor
+        (0: a quarter of the device's free memory)."""
+        import torch
+
         lib = load()
+        dev = torch.device("cuda", ctx.device)
+        if hbm_budget <= 0:
+            free, _ = torch.cuda.mem_get_info(dev)
+            hbm_budget = free // 4
+        hbm_budget = int(hbm_budget) // 256 * 256
+        self.arena = torch.empty(hbm_budget, dtype=torch.uint8, device=dev)
         self._h = ctypes.c_void_p()
         tab = list(tunings or [])
         base = ctx.tuning()
@@ -330,7 +351,8 @@ class Server:
             arr[i] = AopClassTuning(int(m), int(lg), int(p), 0, AopTuning(**dict(base, **sched)))
         self._tab = arr
         cfg = AopServerConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(precision), 0,
-                              ctypes.cast(arr, ctypes.POINTER(AopClassTuning)) if tab else None, len(tab))
+                              ctypes.cast(arr, ctypes.POINTER(AopClassTuning)) if tab else None, len(tab),
+                              ctypes.c_void_p(self.arena.data_ptr()))
         _check(lib.aop_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self._h)), "aop_server_create")
         self.ctx = ctx
 
@@ -351,7 +373,7 @@ class Server:
         return out
 
     def stats(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(len(SERVER_STATS), dtype=np.int64)
         _check(load().aop_server_stats(self._h, out.ctypes.data_as(ctypes.c_void_p)), "aop_server_stats")
         return {f: int(out[i]) for i, f in enumerate(SERVER_STATS)}
 
@@ -359,6 +381,7 @@ class Server:
         if self._h:
             load().aop_server_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self.arena = None
 
     def __del__(self):
         try:

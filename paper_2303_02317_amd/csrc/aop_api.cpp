@@ -294,12 +294,16 @@ const char *aop_status_str(aop_status s)
     return "unknown status";
 }
 
-aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
+size_t aop_twiddle_bytes(void) { return sizeof(double) * 2 * (size_t)aop::TW_N; }
+
+aop_status aop_ctx_create(int device, double lambda, void *d_twiddles, size_t tw_bytes, aop_ctx **out)
 {
     if (!out) return AOP_EINVAL;
     *out = nullptr;
     if (lambda == 0.0) lambda = 1.0 / 3.0;
     if (!(lambda > 0.0 && lambda <= 0.5)) return AOP_EINVAL;
+    if (!d_twiddles || (reinterpret_cast<uintptr_t>(d_twiddles) & 15u) != 0) return AOP_EINVAL;
+    if (tw_bytes < aop_twiddle_bytes()) return AOP_ENOMEM;
     aop_ctx *ctx = new (std::nothrow) aop_ctx;
     if (!ctx) return AOP_ENOMEM;
     ctx->device = device;
@@ -308,10 +312,7 @@ aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
         delete ctx;
         return AOP_EDEVICE;
     }
-    if (hipMalloc(&ctx->d_tw, sizeof(double) * 2 * (size_t)aop::TW_N) != hipSuccess) {
-        delete ctx;
-        return AOP_ENOMEM;
-    }
+    ctx->d_tw = d_twiddles;  // the caller's memory: filled here, never freed here
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
         ncu = 1;
@@ -330,7 +331,7 @@ aop_status aop_ctx_create(int device, double lambda, aop_ctx **out)
     ctx->tuning.timeout_ms = 30000;
     if (hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess ||
         aop::launch_twiddles(ctx->d_tw, nullptr) != 0 || hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(ctx->d_tw);
+        if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
         delete ctx;
         return AOP_EDEVICE;
     }
@@ -345,8 +346,7 @@ aop_status aop_ctx_destroy(aop_ctx *ctx)
     if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
     if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
-    if (ctx->d_tw) (void)hipFree(ctx->d_tw);
-    delete ctx;
+    delete ctx;  // the twiddle table belongs to the caller
     return AOP_OK;
 }
 
@@ -474,7 +474,8 @@ aop_status aop_graph_destroy(aop_graph *g)
 }
 
 aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *opts, int64_t n, void *d_ws,
-                                 size_t ws_bytes, double *d_price, int32_t *h_status, void *stream)
+                                 size_t ws_bytes, double *d_price, int32_t *h_status, int64_t *d_bnd,
+                                 int64_t bnd_stride, void *stream)
 {
     if (!ctx || n < 0 || (n > 0 && (!opts || !d_ws || !d_price))) return AOP_EINVAL;
     if (n == 0) return AOP_OK;
@@ -485,10 +486,16 @@ aop_status aop_price_batch_plain(aop_ctx *ctx, const aop_option *opts, int64_t n
     const size_t need = build_plain(opts, n, ctx->lambda, ctx->h_stage, stat.data());
     if (h_status) std::memcpy(h_status, stat.data(), sizeof(int32_t) * (size_t)n);
     if (ws_bytes < need) return AOP_ENOMEM;
+    if (d_bnd) {
+        int64_t tmax = 0;
+        for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, opts[i].T);
+        if (bnd_stride < tmax + 1) return AOP_EINVAL;
+    }
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(d_ws, ctx->h_stage, sizeof(Desc) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
         return AOP_EDEVICE;
-    if (aop::launch_plain_batch((const Desc *)d_ws, ctx->h_stage, n, (char *)d_ws, d_price, stream) != 0)
+    if (aop::launch_plain_batch((const Desc *)d_ws, ctx->h_stage, n, (char *)d_ws, d_price, d_bnd, bnd_stride,
+                                stream) != 0)
         return AOP_EDEVICE;
     if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
     ctx->stage_pending = true;

@@ -12,7 +12,7 @@
 struct aop_ctx {
     int device = 0;
     double lambda = 1.0 / 3.0;
-    void *d_tw = nullptr;          // twiddle table, TW_N complex doubles
+    void *d_tw = nullptr;          // twiddle table, TW_N complex doubles (the caller's memory)
     aop::Desc *h_stage = nullptr;  // pinned staging for descriptors
     size_t stage_cap = 0;          // descriptors
     hipEvent_t stage_done = nullptr;

@@ -108,6 +108,6 @@ int launch_twiddles(void *d_tw, void *stream);
 int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price,
                  int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, const Tune &tune, void *stream);
 int launch_plain_batch(const Desc *d_desc, const Desc *h_desc, int64_t n, char *d_ws, double *d_price,
-                       void *stream);
+                       int64_t *d_bnd, int64_t bnd_stride, void *stream);
 
 }  // namespace aop

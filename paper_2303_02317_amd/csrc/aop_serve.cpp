@@ -116,6 +116,7 @@ struct Slot {
     std::vector<aop_option> opts;
     aop::Desc *h_desc = nullptr;  // pinned
     double *h_price = nullptr;    // pinned
+    aop::Stats *h_stats = nullptr;  // pinned: the batch's work counters
     int cap = 0;
     size_t off = 0, bytes = 0;
     clock_type::time_point launched;
@@ -147,6 +148,7 @@ struct aop_server {
     bool stop = false;
     aop_status error = AOP_OK;
     int64_t submitted = 0, completed = 0, batches = 0, inflight = 0;
+    int64_t alg_bytes = 0;  // algorithmic HBM bytes of the finished batches (correlation inputs and outputs)
     std::thread worker;
 
     void run();
@@ -184,6 +186,9 @@ bool aop_server::launch(Slot &sl, std::vector<Request> &&batch, size_t bytes)
         return false;
     if (hipMemcpyAsync(sl.h_price, d_price, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
         return false;
+    if (hipMemcpyAsync(sl.h_stats, ws + aop::stats_offset(n), sizeof(aop::Stats) * (size_t)n, hipMemcpyDeviceToHost,
+                       sl.stream) != hipSuccess)
+        return false;
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return false;
     sl.launched = clock_type::now();
     sl.busy = true;
@@ -203,12 +208,16 @@ void aop_server::finish(Slot &sl)
         r.queue_s = seconds_since(sl.reqs[i].submitted, sl.launched);
         r.latency_s = seconds_since(sl.reqs[i].submitted, now);
     }
+    int64_t bytes = 0;
+    for (size_t i = 0; i < sl.reqs.size(); ++i)
+        bytes += 8 * (sl.h_stats[i].conv_in + sl.h_stats[i].conv_out + sl.h_stats[i].direct_cells);
     arena.release(sl.off, sl.bytes);
     sl.busy = false;
     sl.reqs.clear();
     std::lock_guard<std::mutex> g(mu);
     for (auto &r : out) results.push_back(r);
     completed += (int64_t)out.size();
+    alg_bytes += bytes;
     --inflight;
     cv.notify_all();
 }
@@ -347,12 +356,10 @@ aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_ser
     if (c.max_inflight < 1 || c.max_inflight > 16 || c.max_batch < 1 || c.max_batch > 4096 ||
         (c.precision != AOP_FP64 && c.precision != AOP_MIXED) || c.reserved != 0)
         return AOP_EINVAL;
+    if (!c.d_arena || (reinterpret_cast<uintptr_t>(c.d_arena) & (aop::WS_ALIGN - 1)) != 0 ||
+        c.hbm_budget < aop::WS_ALIGN)
+        return AOP_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
-    if (c.hbm_budget == 0) {
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return AOP_EDEVICE;
-        c.hbm_budget = fr / 4;
-    }
     if (c.n_tunings < 0 || (c.n_tunings > 0 && !c.tunings)) return AOP_EINVAL;
     for (int64_t i = 0; i < c.n_tunings; ++i) {
         aop_tuning t = c.tunings[i].tuning;
@@ -365,11 +372,8 @@ aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_ser
     s->cfg = c;
     s->tunings.assign(c.tunings, c.tunings + c.n_tunings);
     s->cfg.tunings = nullptr;
-    s->arena_bytes = aop::ws_align(c.hbm_budget);
-    if (hipMalloc((void **)&s->d_arena, s->arena_bytes) != hipSuccess) {
-        delete s;
-        return AOP_ENOMEM;
-    }
+    s->arena_bytes = c.hbm_budget / aop::WS_ALIGN * aop::WS_ALIGN;
+    s->d_arena = (char *)c.d_arena;  // the caller's memory
     s->arena.reset(s->arena_bytes);
     s->wg_per_batch = std::max(1, std::min(aop::MAX_WG, ctx->n_cu / c.max_inflight));
     s->slots.resize((size_t)c.max_inflight);
@@ -379,7 +383,8 @@ aop_status aop_server_create(aop_ctx *ctx, const aop_server_config *cfg, aop_ser
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_desc, sizeof(aop::Desc) * (size_t)sl.cap, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&sl.h_price, sizeof(double) * (size_t)sl.cap, hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc((void **)&sl.h_price, sizeof(double) * (size_t)sl.cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_stats, sizeof(aop::Stats) * (size_t)sl.cap, hipHostMallocDefault) != hipSuccess)
             st = AOP_EDEVICE;
     }
     if (st != AOP_OK) {
@@ -450,6 +455,7 @@ aop_status aop_server_stats(aop_server *s, int64_t *out)
     out[5] = (int64_t)s->arena.peak();
     out[6] = (int64_t)s->arena_bytes;
     out[7] = s->wg_per_batch;
+    out[8] = s->alg_bytes;
     return AOP_OK;
 }
 
@@ -469,9 +475,9 @@ aop_status aop_server_destroy(aop_server *s)
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.h_desc) (void)hipHostFree(sl.h_desc);
         if (sl.h_price) (void)hipHostFree(sl.h_price);
+        if (sl.h_stats) (void)hipHostFree(sl.h_stats);
     }
-    if (s->d_arena) (void)hipFree(s->d_arena);
-    delete s;
+    delete s;  // the arena belongs to the caller
     return AOP_OK;
 }
 

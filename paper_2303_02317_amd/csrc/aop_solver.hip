@@ -520,13 +520,23 @@ __device__ __forceinline__ double2 kernel_power(const Spec &q, double cs, double
 }
 
 // ------------------------------------------------------ FFT correlation
+// A row value that overflowed FP64 (the top of a lattice row when V sqrt(E T)
+// exceeds ~709) lies so far above the strike that the risk-neutral weight of
+// reaching it is below e^{-T/4}; without exercise (Y = 0 or a European option)
+// nothing stops the plain induction from carrying the infinity to the root, so
+// such a value is left out of the correlation (its product with its weight is
+// far below the rounding of the result).
 __device__ __forceinline__ double tilt_in(double x, double beta, ll t, double tc)
 {
+    if (!(x < INFINITY)) return 0.0;
     return (beta == 0.0 || x == 0.0) ? x : x * exp(-beta * ((double)t - tc));
 }
-__device__ __forceinline__ double tilt_out(double y, double beta, ll m)
+// The untilting factor e^{beta (m - tc)} is applied in one piece: split into
+// e^{beta m} and e^{-beta tc} each part can overflow once beta tc > 709 (a
+// lattice row of T ~ 2^20 cells with V sqrt(E T) above ~700).
+__device__ __forceinline__ double tilt_out(double y, double beta, ll m, double tc)
 {
-    return beta == 0.0 ? y : y * exp(beta * (double)m);
+    return beta == 0.0 ? y : y * exp(beta * ((double)m - tc));
 }
 
 // A correlation job computes dst[t] = (x (*) W^(h))[out_off + t], t < n_out,
@@ -546,8 +556,8 @@ __device__ __forceinline__ double tilt_out(double y, double beta, ll m)
 // Tiles of one phase are independent; a phase starts once the previous one
 // has completed.  With beta != 0 the input is tilted, x~_t = x_t e^{-beta (t -
 // tc)}, the kernel spectrum is tilted to match and the output untilted, y_m =
-// y~_m e^{beta m} (the e^{-beta tc} factor rides in the spectrum), so that a
-// segment growing like e^{beta t} is transformed at uniform relative precision.
+// y~_m e^{beta (m - tc)}, so that a segment growing like e^{beta t} is
+// transformed at uniform relative precision.
 enum { K_DIRECT = 0, K_LDS = 1, K_4STEP = 2 };
 
 struct JobArgs {
@@ -583,7 +593,7 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     const int lgN = j.lgN;
     const ll N = ll(1) << lgN;
     const double invN = 1.0 / (double)N;
-    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const Spec q = make_spec(p, j.h, j.beta, 0.0);
     const int tid = threadIdx.x;
     // unrolled so that several global loads are in flight at once
     if (j.beta == 0.0) {
@@ -616,7 +626,7 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     }
     __syncthreads();
     lds_dit_inv(lds, lgN, 1, twl);
-    for (ll t = tid; t < j.n_out; t += WG) j.dst[t] = tilt_out(lds[j.out_off + t].x * invN, j.beta, j.out_off + t);
+    for (ll t = tid; t < j.n_out; t += WG) j.dst[t] = tilt_out(lds[j.out_off + t].x * invN, j.beta, j.out_off + t, j.tc);
     __syncthreads();
 }
 
@@ -657,7 +667,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N2 = ll(1) << lg2;
-    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const Spec q = make_spec(p, j.h, j.beta, 0.0);
     const int tid = threadIdx.x;
     const int p1 = tile;
     const ll k1 = bitrev(p1, lg1);
@@ -720,7 +730,7 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
         const int c = t & (C - 1), n1 = t >> lgC;
         const ll idx = (ll)n1 * N2 + n20 + c;
         if (idx >= j.out_off && idx < j.out_off + j.n_out)
-            j.dst[idx - j.out_off] = tilt_out(lds[c * N1 + n1].x * invN, j.beta, idx);
+            j.dst[idx - j.out_off] = tilt_out(lds[c * N1 + n1].x * invN, j.beta, idx, j.tc);
     }
     __syncthreads();
 }
@@ -747,7 +757,7 @@ __device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float
     const int lgN = j.lgN;
     const ll N = ll(1) << lgN;
     const double invN = 1.0 / (double)N;
-    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const Spec q = make_spec(p, j.h, j.beta, 0.0);
     const int tid = threadIdx.x;
     for (int t = tid; t < N; t += WG) st_cf(lds + t, cf_from(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0));
     __syncthreads();
@@ -764,7 +774,7 @@ __device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float
     lds_dit_inv_ff(lds, lgN, 1, twf);
     for (ll t = tid; t < j.n_out; t += WG) {
         const CF v = ld_cf(lds + j.out_off + t);
-        j.dst[t] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, j.out_off + t);
+        j.dst[t] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, j.out_off + t, j.tc);
     }
     __syncthreads();
 }
@@ -799,7 +809,7 @@ __device__ __forceinline__ void tile_rows_ff(const Mp &p, const JobArgs &j, int 
 {
     const int lgN = j.lgN, lg2 = LG_NLDS, lg1 = lgN - lg2;
     const ll N2 = ll(1) << lg2;
-    const Spec q = make_spec(p, j.h, j.beta, -j.beta * j.tc);
+    const Spec q = make_spec(p, j.h, j.beta, 0.0);
     const int tid = threadIdx.x;
     const int p1 = tile;
     const ll k1 = bitrev(p1, lg1);
@@ -847,7 +857,7 @@ __device__ __forceinline__ void tile_col_inv_ff(const JobArgs &j, int tile, floa
         const ll idx = (ll)n1 * N2 + n20 + c;
         if (idx >= j.out_off && idx < j.out_off + j.n_out) {
             const CF v = ld_cf(lds + c * N1 + n1);
-            j.dst[idx - j.out_off] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, idx);
+            j.dst[idx - j.out_off] = tilt_out(((double)v.rh + (double)v.rl) * invN, j.beta, idx, j.tc);
         }
     }
     __syncthreads();
@@ -1148,8 +1158,13 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
     const double ku = K * (u - 1.0);
     double g = (j <= b) ? src[j] : ((j <= wr * i0) ? S * exp((double)(cs * j - i0) * a) - K : 0.0);
     int bc = b;
-    for (int k0 = 0; k0 < h; k0 += 64) {
-        const int nb = (h - k0) < 64 ? (h - k0) : 64;
+    // The carried exercise values e <- u e + K(u-1) amplify their rounding by
+    // u per row: blocks (and re-seeding with exp) are cut to at most 4/a rows,
+    // so that the amplification stays below e^4.  Every row length of a
+    // practical lattice (a <= 1/16) keeps the full 64-row block.
+    const int blk = (a * 64.0 <= 4.0) ? 64 : max(1, (int)(4.0 / a));
+    for (int k0 = 0; k0 < h; k0 += blk) {
+        const int nb = (h - k0) < blk ? (h - k0) : blk;
         const int itop = i0 - k0;  // row above the block
         const double e0 = S * exp((double)(cs * j - itop) * a) - K;
         const double f10 = S * exp((double)(cs * (c0 + BAND) - itop) * a) - K;

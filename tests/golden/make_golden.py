@@ -19,6 +19,7 @@ cached under ``--cache`` so that an interrupted run resumes where it stopped.
 
 Usage: python tests/golden/make_golden.py [--threads N] [--only name ...]
                                           [--cache DIR]
+       python tests/golden/make_golden.py --european   (European lattice sums)
 """
 from __future__ import annotations
 
@@ -120,5 +121,38 @@ def main():
         print("wrote", fname, "in %.1fs" % (time.time() - t0), flush=True)
 
 
+# European calls on the lattices at full size: the oracle's O(T) closed-form
+# sums (oracle.european_sum), pinned against its plain induction.
+EUROPEAN_JOBS = [
+    ("binomial", 0, 2, 20, 64),
+    ("trinomial", 1, 3, 20, 64),
+]
+
+
+def write_european():
+    for name, model, cfg, log2T, n in EUROPEAN_JOBS:
+        fname = "oracle_european_%s_c%d_t%d.json" % (name, cfg, log2T)
+        path = os.path.join(HERE, fname)
+        if os.path.exists(path) and json.load(open(path)).get("n_options", 0) >= n:
+            continue
+        opts = inputs.batch(cfg, log2T, 64, model)[:n]
+        t0 = time.time()
+        recs = []
+        for o in opts:
+            price = oracle.european_sum(model, o["S0"], o["K"], o["r"], o["q"], o["sigma"], o["expiry"], o["T"])
+            recs.append(dict(params=dict(o, european=True), price=price))
+        doc = dict(model=model, config=cfg, log2T=log2T, T=1 << log2T, n_options=n, seed=[cfg, log2T],
+                   european=True, method="closed-form sum over the up-move distribution",
+                   wall_seconds=time.time() - t0, options=recs)
+        with open(path + ".tmp", "w") as f:
+            json.dump(doc, f, indent=1)
+        os.replace(path + ".tmp", path)
+        print("wrote", fname, "in %.1fs" % (time.time() - t0), flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--european":
+        oracle.build()
+        write_european()
+    else:
+        main()

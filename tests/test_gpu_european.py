@@ -90,6 +90,24 @@ def test_european_full_size(ctx, oracle_mod, model):
     say("european T=2^20 model", model, "max rel err", worst)
 
 
+@pytest.mark.parametrize("fname", ["oracle_european_binomial_c2_t20.json", "oracle_european_trinomial_c3_t20.json"])
+def test_european_golden_full_size(ctx, fname):
+    # All 64 options of each lattice workload at T = 2^20 against the stored
+    # closed-form oracle sums (tests/golden/make_golden.py --european).
+    import json
+    import os
+
+    doc = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fname)))
+    recs = doc["options"]
+    opts = [r["params"] for r in recs]
+    p, st, _ = run(ctx, opts, boundary=False)
+    fails = [(k, p[k], r["price"]) for k, r in enumerate(recs)
+             if st[k] != 0 or not parity.price_ok(p[k], r["price"], r["params"]["K"])]
+    say(fname, "max rel err", max(parity.price_errors(p[k], r["price"])[1] for k, r in enumerate(recs)
+                                  if abs(r["price"]) >= 1e-3 * r["params"]["K"]))
+    assert not fails, fails[:4]
+
+
 def test_european_and_american_in_one_batch(ctx):
     # Flags are per option: a mixed batch gives each option its solo price.
     from paper_2303_02317_amd import binding
