@@ -156,6 +156,27 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *h_opts, int64_t n, in
                            void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pricing as aop_price_batch, with the workspace taken from a fixed array
+ * inside the library, aop_noalloc_scratch_bytes() = 256 MiB per GPU, which
+ * each GPU the library runs on holds until the process ends.  Allocates
+ * nothing, host or device; the caller passes only the options and the output
+ * buffers (d_price, h_status, d_boundary as in aop_price_batch).
+ * Limits: n <= 256 options and a workspace (aop_workspace_bytes) of at most
+ * 256 MiB -- e.g. one binomial option of T = 2^20, one trinomial option of
+ * T = 2^19, or 64 options of T = 2^14; larger requests return AOP_ENOMEM
+ * before anything is launched.  Every call on one GPU uses the same array and
+ * leaves its contents behind: calls that overlap on one GPU (on different
+ * streams, or from different contexts or threads) race and must be
+ * serialised by the caller.  aop_batch_stats and friends do not apply.
+ */
+aop_status aop_price_batch_noalloc(aop_ctx *ctx, const aop_option *h_opts, int64_t n, int32_t precision,
+                                   double *d_price, int32_t *h_status, int64_t *d_boundary,
+                                   int64_t boundary_stride, void *hip_stream);
+size_t aop_noalloc_scratch_bytes(void);
+
+/*
  * Graph form of aop_price_batch (same method and outputs; the launch form is
  * this library's, the paper runs on CPU cores): the batch's launch (clearing of the work
  * pool and the persistent solve kernel) is captured once in a hipGraph and

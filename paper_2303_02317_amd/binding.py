@@ -28,7 +28,8 @@ EXPORTS = ["aop_twiddle_bytes", "aop_ctx_create", "aop_ctx_destroy", "aop_worksp
            "aop_plain_workspace_bytes", "aop_price_batch_plain", "aop_batch_stats", "aop_price", "aop_sync",
            "aop_status_str", "aop_version", "aop_pool_stats", "aop_pool_abort_info", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
            "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
-           "aop_graph_create", "aop_graph_launch", "aop_graph_destroy", "aop_batch_errors"]
+           "aop_graph_create", "aop_graph_launch", "aop_graph_destroy", "aop_batch_errors",
+           "aop_price_batch_noalloc", "aop_noalloc_scratch_bytes"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
                 "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
@@ -113,6 +114,8 @@ def load():
         "aop_graph_launch": (I32, [P, P]),
         "aop_graph_destroy": (I32, [P]),
         "aop_batch_errors": (I32, [P, I64, P]),
+        "aop_price_batch_noalloc": (I32, [P, P, I64, I32, P, P, P, I64, P]),
+        "aop_noalloc_scratch_bytes": (SZ, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -255,6 +258,32 @@ def price_batch(ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = 
     (stream or torch.cuda.current_stream()).synchronize()
     b = L.boundary.cpu().numpy() if L.boundary is not None else None
     return L.price.cpu().numpy(), L.status.copy(), b
+
+
+def launch_batch_noalloc(ctx: Context, opts, precision: int = AOP_FP64, boundary: bool = False, stream=None,
+                         price=None, bnd=None):
+    """aop_price_batch_noalloc: the library's fixed scratch as workspace.  The
+    outputs are the caller's (given, or made here as torch tensors); the call
+    itself allocates nothing.  Returns (price, status, boundary) without sync."""
+    import torch
+
+    lib = load()
+    n = len(opts)
+    dev = torch.device("cuda", ctx.device)
+    arr = options_array(opts)
+    if price is None:
+        price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    stride = bnd.shape[1] if bnd is not None else 0
+    if boundary and bnd is None:
+        stride = max(int(o["T"]) for o in opts) + 1 if n else 0
+        bnd = torch.empty((max(n, 1), max(stride, 1)), dtype=torch.int64, device=dev)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib.aop_price_batch_noalloc(ctx.handle, arr, n, int(precision), ctypes.c_void_p(price.data_ptr()),
+                                     status.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.c_void_p(bnd.data_ptr()) if bnd is not None else None, stride,
+                                     _stream_handle(stream))
+    _check(rc, "aop_price_batch_noalloc")
+    return price[:n], status[:n], (bnd[:n] if bnd is not None else None)
 
 
 def launch_plain(ctx: Context, opts, stream=None, workspace=None, boundary: bool = False):

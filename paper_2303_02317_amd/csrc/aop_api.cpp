@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -183,6 +184,76 @@ static double option_cost(const Desc &d)
 // are stored in decreasing order of estimated cost (the order in which the
 // persistent kernel's workgroups claim them); out_index keeps each option's
 // position in the caller's arrays.
+
+// Descriptors of a batch built straight into `out` (n entries) without any
+// heap allocation: stable insertion sort by decreasing cost (small n only).
+size_t build_batch_in_place(const aop_option *opts, int64_t n, int32_t prec, double lambda, Desc *out,
+                            int32_t *status)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        Desc &d = out[i];
+        aop_status st = make_desc(opts[i], lambda, d);
+        if (st == AOP_OK && prec != AOP_FP64 && prec != AOP_MIXED) st = AOP_EINVAL;
+        d.out_index = i;
+        d.prec = prec;
+        if (status) status[i] = st;
+        if (st != AOP_OK) {
+            d.model = -1;
+            continue;
+        }
+        geometry(d);
+    }
+    for (int64_t i = 1; i < n; ++i) {
+        const Desc x = out[i];
+        const double cx = option_cost(x);
+        int64_t k = i;
+        while (k > 0 && option_cost(out[k - 1]) < cx) {
+            out[k] = out[k - 1];
+            --k;
+        }
+        out[k] = x;
+    }
+    size_t off = (size_t)aop::options_offset(n);
+    for (int64_t k = 0; k < n; ++k)
+        if (out[k].model >= 0) {
+            out[k].ws_off = (int64_t)off;
+            off += option_bytes(out[k]);
+        }
+    return off;
+}
+
+// Workspace of aop_price_batch_noalloc: a fixed device array, one per GPU.
+// Host code never passes `scratch` itself to a kernel or copy: its address on
+// each device comes from hipGetSymbolAddress, taken once per device when a
+// context is created there (with that device current).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+constexpr int64_t NOALLOC_MAX_OPTIONS = 256;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+// With `device` current: resolve this device's copy of `scratch` (once).
+aop_status scratch_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return AOP_EINVAL;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return AOP_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return AOP_EDEVICE;
+    g_scratch_ptr[device] = ptr;
+    return AOP_OK;
+}
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 }  // namespace
 
 namespace aop {
@@ -313,6 +384,10 @@ aop_status aop_ctx_create(int device, double lambda, void *d_twiddles, size_t tw
         return AOP_EDEVICE;
     }
     ctx->d_tw = d_twiddles;  // the caller's memory: filled here, never freed here
+    if (scratch_setup(device) != AOP_OK) {
+        delete ctx;
+        return AOP_EDEVICE;
+    }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
         ncu = 1;
@@ -334,6 +409,12 @@ aop_status aop_ctx_create(int device, double lambda, void *d_twiddles, size_t tw
         if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
         delete ctx;
         return AOP_EDEVICE;
+    }
+    // descriptor staging sized for aop_price_batch_noalloc, which must not allocate
+    if (ensure_stage(ctx, (size_t)NOALLOC_MAX_OPTIONS) != AOP_OK) {
+        (void)hipEventDestroy(ctx->stage_done);
+        delete ctx;
+        return AOP_ENOMEM;
     }
     *out = ctx;
     return AOP_OK;
@@ -396,6 +477,43 @@ aop_status aop_price_batch(aop_ctx *ctx, const aop_option *opts, int64_t n, int3
         return AOP_EDEVICE;
     return AOP_OK;
 }
+
+aop_status aop_price_batch_noalloc(aop_ctx *ctx, const aop_option *opts, int64_t n, int32_t precision,
+                                   double *d_price, int32_t *h_status, int64_t *d_bnd, int64_t bnd_stride,
+                                   void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!opts || !d_price))) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    if (n > NOALLOC_MAX_OPTIONS || ctx->stage_cap < (size_t)n) return AOP_ENOMEM;
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    char *ws = (char *)scratch_of(ctx->device);
+    if (!ws) return AOP_EDEVICE;
+    if (ctx->stage_pending) {  // the staging buffer's previous copy must have left it
+        if (hipEventSynchronize(ctx->stage_done) != hipSuccess) return AOP_EDEVICE;
+        ctx->stage_pending = false;
+    }
+    int32_t st_local[NOALLOC_MAX_OPTIONS];
+    int32_t *st = h_status ? h_status : st_local;
+    const size_t need = build_batch_in_place(opts, n, precision, ctx->lambda, ctx->h_stage, st);
+    if (need > NOALLOC_SCRATCH_BYTES) return AOP_ENOMEM;
+    if (d_bnd) {
+        int64_t tmax = 0;
+        for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, opts[i].T);
+        if (bnd_stride < tmax + 1) return AOP_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(ws, ctx->h_stage, sizeof(Desc) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AOP_EDEVICE;
+    if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
+    ctx->stage_pending = true;
+    aop::Tune tune = aop::make_tune(*ctx, 0);
+    tune.prec = precision;
+    if (aop::launch_solve((const Desc *)ws, n, ws, ctx->d_tw, d_price, d_bnd, bnd_stride, nullptr, tune, stream) != 0)
+        return AOP_EDEVICE;
+    return AOP_OK;
+}
+
+size_t aop_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 aop_status aop_plain_workspace_bytes(const aop_option *opts, int64_t n, size_t *bytes)
 {
