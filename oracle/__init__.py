@@ -93,6 +93,25 @@ def european_sum(model: int, S: float, K: float, r: float, q: float, sigma: floa
     return out.value
 
 
+GAUSS_WINDOW, GAUSS_SUM, GAUSS_ERF = 0, 1, 2
+
+
+def european_gauss(method: int, S: float, K: float, r: float, q: float, sigma: float, expiry: float, T: int,
+                   lib=None) -> float:
+    """Gaussian approximations of the European binomial call: method 0 the
+    O(sqrt T) windowed sum, 1 the O(T) sum, 2 the O(1) erf closed form."""
+    lib = lib or _lib()
+    f = lib.aop_oracle_european_gauss
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6 + [ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    out = ctypes.c_double(0.0)
+    rc = f(int(method), float(S), float(K), float(r), float(q), float(sigma), float(expiry), int(T),
+           ctypes.byref(out))
+    if rc != 0:
+        raise OracleError("oracle rejected option: %s" % _STATUS.get(rc, rc))
+    return out.value
+
+
 def load_variant(so_path: str):
     """Load another build of the oracle source (used by the mutation tests)."""
     return _declare(ctypes.CDLL(so_path))

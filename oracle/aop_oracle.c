@@ -395,6 +395,67 @@ int aop_oracle_european_sum(int model, double S, double K, double r, double q, d
 }
 
 /*
+ * Gaussian approximations of the European binomial call (the paper's section
+ * on the European call under the binomial model): the number of up moves x of
+ * the T-step lattice is approximated by a normal density with mean pT and
+ * variance v = p(1-p)T, so that
+ *   price ~ m^T / sqrt(2 pi v) * sum_x (S u^{2x-T} - K)^+ e^{-(x - pT)^2 / (2v)}.
+ * method 0: the sum over x in [max(pT - 6 sqrt v, 0), min(pT + 6 sqrt v, T) - 1]
+ *           (x integer, the window bounds rounded up), O(sqrt T) terms;
+ * method 1: the sum over x in [0, T-1], O(T) terms;
+ * method 2: the integral of the same density times (S u^{2x-T} - K) from
+ *           x0 = ceil(T/2 + ln(K/S) / (2 ln u)) to T, in closed form with erf:
+ *           m^T/2 [ S u^{2(v ln u + pT) - T} erf((x - pT)/sqrt(2v) - ln u sqrt(2v))
+ *                   - K erf((x - pT)/sqrt(2v)) ] from x0 to T, O(1).
+ * (The paper writes the mean as -pT inside (x + mu); the same density.)
+ */
+int aop_oracle_european_gauss(int method, double S, double K, double r, double q, double sigma, double E,
+                              int64_t T, double *price)
+{
+    if (!price || method < 0 || method > 2)
+        return OR_EINVAL;
+    if (!(isfinite(S) && isfinite(K) && isfinite(r) && isfinite(q) && isfinite(sigma) &&
+          isfinite(E)) ||
+        S <= 0.0 || K <= 0.0 || sigma <= 0.0 || E <= 0.0 || T < 1 || q < 0.0)
+        return OR_EINVAL;
+    const double dt = E / (double)T;
+    const double a = sigma * sqrt(dt); /* ln u */
+    const double u = exp(a), d = 1.0 / u;
+    const double p = (exp((r - q) * dt) - d) / (u - d);
+    const double m = exp(-r * dt);
+    if (!(p > 0.0 && p < 1.0))
+        return OR_EPROB;
+    const double mu = p * (double)T;
+    const double v = p * (1.0 - p) * (double)T;
+    const double disc = pow(m, (double)T);
+    if (method == 2) {
+        const double x0 = ceil(0.5 * (double)T + log(K / S) / (2.0 * a));
+        const double lo = x0 > (double)T ? (double)T : x0;
+        const double sv2 = sqrt(2.0 * v);
+        const double gS = S * exp((2.0 * (v * a + mu) - (double)T) * a);
+        const double sterm = gS * (erf(((double)T - mu) / sv2 - a * sv2) - erf((lo - mu) / sv2 - a * sv2));
+        const double kterm = K * (erf(((double)T - mu) / sv2) - erf((lo - mu) / sv2));
+        *price = 0.5 * disc * (sterm - kterm);
+        return OR_OK;
+    }
+    int64_t xlo = 0, xhi = T - 1;
+    if (method == 0) {
+        const double sd = sqrt(v);
+        const double lo = ceil(mu - 6.0 * sd), hi = ceil(mu + 6.0 * sd);
+        xlo = lo > 0.0 ? (int64_t)lo : 0;
+        xhi = (hi < (double)T ? (int64_t)hi : T) - 1;
+    }
+    double acc = 0.0;
+    for (int64_t x = xlo; x <= xhi; ++x) {
+        const double pay = S * exp((double)(2 * x - T) * a) - K;
+        if (pay > 0.0)
+            acc += pay * exp(-((double)x - mu) * ((double)x - mu) / (2.0 * v));
+    }
+    *price = disc * acc / sqrt(2.0 * M_PI * v);
+    return OR_OK;
+}
+
+/*
  * Entry point.  model: 0 binomial call, 1 trinomial call, 2 BSM put.
  * boundary: NULL or T+1 entries; margin: NULL or 2(T+1) entries.
  * lambda: dtau/ds^2 for the BSM grid (ignored otherwise).

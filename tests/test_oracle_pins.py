@@ -524,3 +524,62 @@ def test_european_sum_against_high_precision(oracle_mod, model):
                 exact = pins.mp_trinomial(S, K, r, q, s, E, min(T, 400), american=False)
                 got = oracle_mod.european_sum(model, S, K, r, q, s, E, min(T, 400))
             assert abs(got - float(exact)) <= 1e-12 * float(exact), (got, exact)
+
+
+# ------------------------------- Gaussian / erf European approximations
+GP = [(100.0, 95.0, 0.05, 0.02, 0.3, 1.2), (80.0, 120.0, 0.03, 0.01, 0.45, 2.0), (130.0, 70.0, 0.07, 0.05, 0.15, 0.5)]
+
+
+@pytest.mark.parametrize("prm", GP)
+def test_gauss_erf_form_is_the_integral(oracle_mod, prm):
+    # The O(1) form is the closed-form integral of the same Gaussian-weighted
+    # payoff from ceil(T/2 + ln(K/S)/(2 ln u)) to T: checked by quadrature.
+    from scipy import integrate
+
+    S, K, r, q, s, E = prm
+    for T in (64, 1000, 50000):
+        dt, u, _, p, m = pins.bopm_params(r, q, s, E, T)
+        mu, v, lu = p * T, p * (1 - p) * T, math.log(u)
+        x0 = math.ceil(T / 2 + math.log(K / S) / (2 * lu))
+        f = lambda x: (S * math.exp((2 * x - T) * lu) - K) * math.exp(-(x - mu) ** 2 / (2 * v))
+        lo = min(x0, T)
+        pts = [c for c in (mu - 8 * math.sqrt(v), mu, mu + 8 * math.sqrt(v)) if lo < c < T]
+        val, _ = integrate.quad(f, lo, T, points=pts or None, limit=400, epsabs=0, epsrel=1e-13)
+        ref = m ** T * val / math.sqrt(2 * math.pi * v)
+        got = oracle_mod.european_gauss(oracle_mod.GAUSS_ERF, S, K, r, q, s, E, T)
+        assert abs(got - ref) <= 1e-9 * max(abs(ref), 1e-3 * K), (T, got, ref)
+
+
+@pytest.mark.parametrize("prm", GP)
+def test_gauss_sums_approximate_the_lattice(oracle_mod, prm):
+    # The normal approximation of the up-move count is a local limit theorem:
+    # its sums approach the exact binomial sum with an error of order 1/T
+    # (a wrong mean, variance or discount would not converge at all), and as
+    # T grows all three forms approach Black-Scholes with a dividend yield.
+    S, K, r, q, s, E = prm
+    errs = []
+    for T in (1000, 10000, 100000):
+        ex = oracle_mod.european_sum(0, S, K, r, q, s, E, T)
+        full = oracle_mod.european_gauss(oracle_mod.GAUSS_SUM, S, K, r, q, s, E, T)
+        errs.append(abs(full - ex) / ex)
+    assert errs[0] < 2e-3
+    assert 4.0 < errs[0] / errs[1] < 25.0 and 4.0 < errs[1] / errs[2] < 25.0, errs
+    T = 1 << 20
+    bs = pins.bs_call_div(S, K, r, q, s, E)
+    for meth in (oracle_mod.GAUSS_WINDOW, oracle_mod.GAUSS_SUM, oracle_mod.GAUSS_ERF):
+        assert abs(oracle_mod.european_gauss(meth, S, K, r, q, s, E, T) - bs) <= 2e-3 * bs
+
+
+def test_gauss_window_covers_the_mass(oracle_mod):
+    # The O(sqrt T) window is the full sum cut at 6 standard deviations: equal
+    # to it when the window spans every x, and within the Gaussian tail beyond
+    # 6 sd otherwise.
+    S, K, r, q, s, E = GP[0]
+    for T in (8, 16, 30):  # mu +- 6 sd covers [0, T-1]
+        w = oracle_mod.european_gauss(oracle_mod.GAUSS_WINDOW, S, K, r, q, s, E, T)
+        f = oracle_mod.european_gauss(oracle_mod.GAUSS_SUM, S, K, r, q, s, E, T)
+        assert w == f
+    for T in (4096, 1 << 20):
+        w = oracle_mod.european_gauss(oracle_mod.GAUSS_WINDOW, S, K, r, q, s, E, T)
+        f = oracle_mod.european_gauss(oracle_mod.GAUSS_SUM, S, K, r, q, s, E, T)
+        assert 0 <= f - w <= 1e-6 * f
