@@ -18,7 +18,9 @@ workload) through the C ABI.  Prints one JSON line:
                and the FFT path's speed-up over it
   extra        the other seeded workloads (trinomial mixed precision 2^20,
                BSM 2^18 FP64 and mixed, European 2^20), each with its
-               throughput and per-option errors
+               throughput and per-option errors, and the Gaussian
+               approximations of the European binomial call with their error
+               against the exact lattice value
   serve        the serving mix: capacity, p50/p99 latency at 0.7 capacity,
                and the served batches' algorithmic bytes against HBM peak
   cpu_baseline the CPU oracle (plain Theta(T^2) induction) on a bounded
@@ -272,6 +274,30 @@ def serve_bench(ctx, n_req: int, load: float = 0.7, max_inflight: int = 4, max_b
             "all_ok": ok, "same_prices_both_runs": same}
 
 
+def approx_leg(ctx, n=64, log2T=20):
+    """Gaussian approximations of the European binomial call: time per batch
+    and error against the exact lattice value (stored oracle sums)."""
+    import torch
+
+    from paper_2303_02317_amd import binding, inputs
+
+    opts = inputs.batch(CONFIG_ID[0], log2T, n, 0)
+    ref = golden_prices(0, log2T, european=True)
+    out = {}
+    for method, name in ((0, "window_6sd_O(sqrt T)"), (1, "sum_O(T)"), (2, "erf_O(1)")):
+        binding.european_approx(ctx, opts, method)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, st = binding.european_approx(ctx, opts, method)
+        dt = time.perf_counter() - t0
+        rel = [abs(p[i] - ref[i]) / ref[i] for i in range(min(len(ref), n)) if ref[i] >= 1e-3 * opts[i]["K"]] \
+            if ref else []
+        out[name] = {"ms_per_batch": dt * 1e3, "max_rel_err_vs_exact_lattice": max(rel) if rel else None,
+                     "all_status_ok": bool((st == 0).all())}
+    return {"workload": "European binomial call, T=2^%d, %d seeded options (approximations of the lattice value)"
+                        % (log2T, n), "methods": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +442,7 @@ def main():
             "bsm_mixed_T2p18": extra_leg(ctx, "config 4", 2, 18, 1),
             "binomial_european_T2p20": extra_leg(ctx, "European", 0, 20, 0, european=True),
             "trinomial_european_T2p20": extra_leg(ctx, "European", 1, 20, 0, european=True),
+            "binomial_european_gauss_approx_T2p20": approx_leg(ctx),
         }
         autotune.apply(ctx, model, 1 << args.log2T, 0)
     if args.serve_requests > 0:

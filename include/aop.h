@@ -177,6 +177,29 @@ aop_status aop_price_batch_noalloc(aop_ctx *ctx, const aop_option *h_opts, int64
 size_t aop_noalloc_scratch_bytes(void);
 
 /*
+ * Gaussian approximations of the European binomial call (the paper's section
+ * on the European call under the binomial model): the up-move count of the
+ * T-step lattice (Fig. 1) is replaced by a normal variable with mean pT and
+ * variance p(1-p)T, and the price m^T E[(S u^{2x-T} - K)^+] is taken as
+ *   method 0  the sum over integer x within 6 standard deviations of the
+ *             mean (clipped to [0, T-1]): O(sqrt T) terms;
+ *   method 1  the sum over x in [0, T-1]: O(T) terms;
+ *   method 2  the integral over x from ceil(T/2 + ln(K/S)/(2 ln u)) to T in
+ *             closed form with erf: O(1).
+ * These are approximations of the lattice value (error of order 1/T for the
+ * sums, larger for the integral), not the lattice value itself: the exact
+ * European price is aop_price_batch with AOP_EUROPEAN.  Only
+ * AOP_BINOMIAL_CALL is covered (others get status AOP_ENOTIMPL, price NaN);
+ * exercise flags are ignored.  d_workspace: aop_approx_workspace_bytes(n)
+ * device bytes (caller-owned); d_price: n doubles; h_status: n int32 (written
+ * before return).  Asynchronous on hip_stream.
+ */
+size_t aop_approx_workspace_bytes(int64_t n);
+aop_status aop_european_approx(aop_ctx *ctx, const aop_option *h_opts, int64_t n, int32_t method,
+                               void *d_workspace, size_t ws_bytes, double *d_price, int32_t *h_status,
+                               void *hip_stream);
+
+/*
  * Graph form of aop_price_batch (same method and outputs; the launch form is
  * this library's, the paper runs on CPU cores): the batch's launch (clearing of the work
  * pool and the persistent solve kernel) is captured once in a hipGraph and

@@ -29,7 +29,8 @@ EXPORTS = ["aop_twiddle_bytes", "aop_ctx_create", "aop_ctx_destroy", "aop_worksp
            "aop_status_str", "aop_version", "aop_pool_stats", "aop_pool_abort_info", "aop_ctx_get_tuning", "aop_ctx_set_tuning",
            "aop_server_create", "aop_server_submit", "aop_server_poll", "aop_server_stats", "aop_server_destroy",
            "aop_graph_create", "aop_graph_launch", "aop_graph_destroy", "aop_batch_errors",
-           "aop_price_batch_noalloc", "aop_noalloc_scratch_bytes"]
+           "aop_price_batch_noalloc", "aop_noalloc_scratch_bytes", "aop_approx_workspace_bytes",
+           "aop_european_approx"]
 
 STATS_FIELDS = ["convs", "conv_in", "conv_out", "fft_points", "band_rows", "direct_cells", "max_depth",
                 "trapezoids", "n_direct", "n_fft", "cyc_band", "cyc_tiles", "cyc_wait", "cyc_rows", "cyc_total",
@@ -116,6 +117,8 @@ def load():
         "aop_batch_errors": (I32, [P, I64, P]),
         "aop_price_batch_noalloc": (I32, [P, P, I64, I32, P, P, P, I64, P]),
         "aop_noalloc_scratch_bytes": (SZ, []),
+        "aop_approx_workspace_bytes": (SZ, [I64]),
+        "aop_european_approx": (I32, [P, P, I64, I32, P, SZ, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -284,6 +287,28 @@ def launch_batch_noalloc(ctx: Context, opts, precision: int = AOP_FP64, boundary
                                      _stream_handle(stream))
     _check(rc, "aop_price_batch_noalloc")
     return price[:n], status[:n], (bnd[:n] if bnd is not None else None)
+
+
+GAUSS_WINDOW, GAUSS_SUM, GAUSS_ERF = 0, 1, 2
+
+
+def european_approx(ctx: Context, opts, method: int, stream=None):
+    """aop_european_approx: Gaussian approximations of European binomial calls.
+    Returns (prices as numpy, status) after synchronising the stream."""
+    import torch
+
+    lib = load()
+    n = len(opts)
+    dev = torch.device("cuda", ctx.device)
+    ws = torch.empty(int(lib.aop_approx_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    price = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    _check(lib.aop_european_approx(ctx.handle, options_array(opts), n, int(method), ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), ctypes.c_void_p(price.data_ptr()),
+                                   status.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)),
+           "aop_european_approx")
+    (stream or torch.cuda.current_stream()).synchronize()
+    return price[:n].cpu().numpy(), status[:n]
 
 
 def launch_plain(ctx: Context, opts, stream=None, workspace=None, boundary: bool = False):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libaop.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["aop_solver.hip", "aop_plain.hip", "aop_api.cpp", "aop_serve.cpp"]
+SOURCES = ["aop_solver.hip", "aop_plain.hip", "aop_approx.hip", "aop_api.cpp", "aop_serve.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -515,6 +515,59 @@ aop_status aop_price_batch_noalloc(aop_ctx *ctx, const aop_option *opts, int64_t
 
 size_t aop_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
+size_t aop_approx_workspace_bytes(int64_t n) { return align_up(sizeof(aop::ApproxParam) * (size_t)std::max<int64_t>(n, 1)); }
+
+aop_status aop_european_approx(aop_ctx *ctx, const aop_option *opts, int64_t n, int32_t method, void *d_ws,
+                               size_t ws_bytes, double *d_price, int32_t *h_status, void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!opts || !d_ws || !d_price)) || method < 0 || method > 2) return AOP_EINVAL;
+    if (n == 0) return AOP_OK;
+    if (ws_bytes < aop_approx_workspace_bytes(n)) return AOP_ENOMEM;
+    if (hipSetDevice(ctx->device) != hipSuccess) return AOP_EDEVICE;
+    // the parameters (80 B each) are staged in the descriptor buffer (128 B each)
+    aop_status st = ensure_stage(ctx, (size_t)n);
+    if (st != AOP_OK) return st;
+    aop::ApproxParam *prm = reinterpret_cast<aop::ApproxParam *>(ctx->h_stage);
+    for (int64_t i = 0; i < n; ++i) {
+        const aop_option &o = opts[i];
+        aop::ApproxParam &q = prm[i];
+        std::memset(&q, 0, sizeof(q));
+        Desc d;
+        aop_status s = make_desc(o, ctx->lambda, d);
+        if (s == AOP_OK && o.model != AOP_BINOMIAL_CALL) s = AOP_ENOTIMPL;  // the section covers the binomial call
+        if (h_status) h_status[i] = s;
+        if (s != AOP_OK) continue;
+        // Fig. 1: dt = E/T, u = e^{V sqrt(dt)}, p = (e^{(R-Y)dt} - 1/u)/(u - 1/u), m = e^{-R dt}
+        const double T = (double)o.T, dt = o.expiry / T;
+        const double a = o.sigma * std::sqrt(dt), u = std::exp(a), dn = 1.0 / u;
+        const double p = (std::exp((o.r - o.q) * dt) - dn) / (u - dn);
+        q.S = o.S0;
+        q.K = o.K;
+        q.a = a;
+        q.mu = p * T;
+        q.v = p * (1.0 - p) * T;
+        q.disc = std::pow(std::exp(-o.r * dt), T);
+        q.T = o.T;
+        q.method = method;
+        q.valid = 1;
+        q.xlo = 0;
+        q.xhi = o.T - 1;
+        if (method == 0) {  // mean +- 6 standard deviations, clipped to [0, T-1]
+            const double sd = std::sqrt(q.v);
+            const double lo = std::ceil(q.mu - 6.0 * sd), hi = std::ceil(q.mu + 6.0 * sd);
+            q.xlo = lo > 0.0 ? (int64_t)lo : 0;
+            q.xhi = (hi < T ? (int64_t)hi : o.T) - 1;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(d_ws, prm, sizeof(aop::ApproxParam) * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AOP_EDEVICE;
+    if (hipEventRecord(ctx->stage_done, s) != hipSuccess) return AOP_EDEVICE;
+    ctx->stage_pending = true;
+    if (aop::launch_approx((const aop::ApproxParam *)d_ws, n, d_price, stream) != 0) return AOP_EDEVICE;
+    return AOP_OK;
+}
+
 aop_status aop_plain_workspace_bytes(const aop_option *opts, int64_t n, size_t *bytes)
 {
     if (!bytes || n < 0 || (n > 0 && !opts)) return AOP_EINVAL;

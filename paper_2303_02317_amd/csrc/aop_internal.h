@@ -103,10 +103,25 @@ constexpr int DIRECT_MAX_H = 448;   // deepest directly stepped correlation (its
 constexpr int LG_TW = 22;  // twiddle table: e^{-2 pi i t / 2^22}, t < 2^22
 constexpr int64_t TW_N = int64_t(1) << LG_TW;
 
-// Host-side launchers (defined in aop_solver.hip / aop_plain.hip).
+// Parameters of one Gaussian approximation of a European binomial call
+// (80 bytes; built on the host from Fig. 1's lattice parameters).
+struct ApproxParam {
+    double S, K;      // spot, strike
+    double a;         // ln u = V sqrt(dt)
+    double mu, v;     // mean pT and variance p(1-p)T of the up-move count
+    double disc;      // m^T
+    int64_t T;
+    int32_t method;   // 0 window of 6 sd, 1 sum over [0, T-1], 2 erf closed form
+    int32_t valid;    // 0: rejected on the host (price NaN)
+    int64_t xlo, xhi; // summation range (methods 0 and 1)
+};
+static_assert(sizeof(ApproxParam) == 80, "approximation parameters are 80 bytes");
+
+// Host-side launchers (defined in aop_solver.hip / aop_plain.hip / aop_approx.hip).
 int launch_twiddles(void *d_tw, void *stream);
 int launch_solve(const Desc *d_desc, int64_t n, char *d_ws, const void *d_tw, double *d_price,
                  int64_t *d_bnd, int64_t bnd_stride, int32_t *d_err, const Tune &tune, void *stream);
+int launch_approx(const ApproxParam *d_prm, int64_t n, double *d_price, void *stream);
 int launch_plain_batch(const Desc *d_desc, const Desc *h_desc, int64_t n, char *d_ws, double *d_price,
                        int64_t *d_bnd, int64_t bnd_stride, void *stream);
 
