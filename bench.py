@@ -25,6 +25,8 @@ workload) through the C ABI.  Prints one JSON line:
                and the served batches' algorithmic bytes against HBM peak
   cpu_baseline the CPU oracle (plain Theta(T^2) induction) on a bounded
                sample, one option per host thread
+  cpu_fft_method the same FFT method on host cores (OpenMP) at the paper's
+               parameter point, by thread count
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2T 20]
                        [--options 64] [--option-type binomial|trinomial|bsm]
@@ -298,6 +300,33 @@ def approx_leg(ctx, n=64, log2T=20):
                         % (log2T, n), "methods": out}
 
 
+def cpu_method_leg():
+    """The method itself on host cores (libaop_cpu, OpenMP tasks) at the paper's
+    parameter point (Sec. 5), binomial call, T = 2^15 and 2^19, by thread
+    count: the shape of the paper's scalability table on this machine's cores."""
+    from paper_2303_02317_amd import cpu, inputs
+
+    P = inputs.PAPER_POINT
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    out = {"workload": "binomial American call at the paper's parameter point (S=127.62, K=130, R=0.00163, "
+                       "Y=0.0163, V=0.2, E=252/365 y), one option", "cores_available": cores, "runs": []}
+    for log2T, threads, reps in ((15, (1, 2, 4, 8, 16), 3), (19, (1, 16), 1)):
+        o = inputs.option(0, P["S0"], P["K"], P["r"], P["q"], P["sigma"], P["expiry"], 1 << log2T)
+        for th in threads:
+            if th > cores:
+                continue
+            best = None
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                pr, st, _ = cpu.price_batch([o], threads=th, base=8)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            out["runs"].append({"T": 1 << log2T, "threads": th, "ms": best * 1e3, "price": float(pr[0]),
+                                "cells_per_s": float(1 << log2T) ** 2 / best})
+    log("cpu method: %s" % ["T=%d p=%d %.1f ms" % (r["T"], r["threads"], r["ms"]) for r in out["runs"]])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +480,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(opts, model, args.log2T)
+        line["cpu_fft_method"] = cpu_method_leg()
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -32,8 +32,28 @@ def _compile(src: str, obj: str) -> None:
         raise RuntimeError("hipcc failed on %s" % os.path.basename(src))
 
 
+CPU_SRC = os.path.join(CSRC, "aop_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "libaop_cpu.so")
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """Compile libaop_cpu.so (the host multicore form of the method) with g++ and OpenMP."""
+    tmp = CPU_LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O3", "-std=c++17", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-I", INCLUDE, "-o", tmp, CPU_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("g++ failed on aop_cpu.cpp")
+    os.replace(tmp, CPU_LIB)
+    if verbose:
+        print("built", CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libaop.so; always rebuilds."""
+    """Compile every source and link libaop.so, and libaop_cpu.so; always rebuilds."""
+    build_cpu(verbose)
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     jobs = []
