@@ -119,8 +119,14 @@ def load_variant(so_path: str):
 
 def price(model: int, S: float, K: float, r: float, q: float, sigma: float, expiry: float,
           T: int, american: bool = True, lam: float = DEFAULT_LAMBDA,
-          boundary: bool = False, margin: bool = False, lib=None):
+          boundary: bool = False, margin: bool = False, lib=None, every: int | None = None):
     """Price one option by plain backward induction.
+
+    ``every`` (binomial call only) overrides ``american``: 1 American, 0
+    European, d >= 2 the Bermudan call exercisable on the rows i with
+    (T - i) % d == 0 (every d steps back from expiry); its boundary on the
+    other rows is the row's last column (every cell continues) and its margins
+    there are NaN.
 
     Returns the price, or ``(price, boundary, margin)`` when either array is
     requested (``None`` for the one not requested).  ``boundary`` has T+1
@@ -134,8 +140,9 @@ def price(model: int, S: float, K: float, r: float, q: float, sigma: float, expi
     out = ctypes.c_double(0.0)
     b = np.empty(T + 1, dtype=np.int64) if boundary else None
     mg = np.empty(2 * (T + 1), dtype=np.float64) if margin else None
+    ex = (1 if american else 0) if every is None else int(every)
     rc = lib.aop_oracle_price(int(model), float(S), float(K), float(r), float(q), float(sigma),
-                              float(expiry), int(T), 1 if american else 0, float(lam),
+                              float(expiry), int(T), ex, float(lam),
                               ctypes.byref(out),
                               b.ctypes.data if b is not None else None,
                               mg.ctypes.data if mg is not None else None)
@@ -147,7 +154,12 @@ def price(model: int, S: float, K: float, r: float, q: float, sigma: float, expi
 
 
 def price_option(opt: dict, **kw):
-    """``price`` for an option dict with keys model, S0, K, r, q, sigma, expiry, T."""
+    """``price`` for an option dict with keys model, S0, K, r, q, sigma, expiry, T
+    (and optionally european=True, or exercise_every=d for a Bermudan call)."""
+    if opt.get("european") and "american" not in kw and "every" not in kw:
+        kw = dict(kw, american=False)
+    if opt.get("exercise_every", 1) != 1 and "every" not in kw:
+        kw = dict(kw, every=int(opt["exercise_every"]))
     return price(opt["model"], opt["S0"], opt["K"], opt["r"], opt["q"], opt["sigma"],
                  opt["expiry"], opt["T"], **kw)
 

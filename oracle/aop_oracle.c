@@ -62,7 +62,7 @@ static int is_red(double c, double e)
  * (Margins are decision gaps in units of the strike; -inf marks non-finite.)
  */
 static int oracle_binomial(double S, double K, double r, double q, double sigma, double E,
-                           int64_t T, int american, double *price, int64_t *boundary,
+                           int64_t T, int64_t every, double *price, int64_t *boundary,
                            double *margin)
 {
     const double dt = E / (double)T;
@@ -102,10 +102,15 @@ static int oracle_binomial(double S, double K, double r, double q, double sigma,
     }
 
     /* Rows T-1 .. 0, in place: G[j] <- f(G[j], G[j+1]).  The three loop
-     * bodies are the same recurrence; they differ only in what they record. */
+     * bodies are the same recurrence; they differ only in what they record.
+     * every: 1 American (exercise on every row), 0 European (never before
+     * expiry), d >= 2 Bermudan: exercise on the rows i with (T - i) % d == 0,
+     * every d steps back from expiry; on the other rows every cell is a
+     * continuation (red) cell. */
     double gap_last = NAN, gap_next = NAN; /* decision gaps at the last red cell and the next */
     for (int64_t i = T - 1; i >= 0; --i) {
         last = -1;
+        const int american = every == 1 || (every > 1 && (T - i) % every == 0);
         if (!american) {
             for (int64_t j = 0; j <= i; ++j)
                 G[j] = w_dn * G[j] + w_up * G[j + 1];
@@ -131,10 +136,13 @@ static int oracle_binomial(double S, double K, double r, double q, double sigma,
                 prev_red = red;
             }
         }
-        if (boundary) boundary[i] = american ? last : -1;
+        if (boundary) boundary[i] = american ? last : (every == 0 ? -1 : i);
         if (margin && american) {
             margin[2 * i] = last >= 0 ? gap_last : NAN;
             margin[2 * i + 1] = (last + 1 <= i) ? gap_next : NAN;
+        } else if (margin && every > 1) {
+            margin[2 * i] = NAN;
+            margin[2 * i + 1] = NAN;
         }
     }
     *price = G[0];
@@ -466,6 +474,10 @@ int aop_oracle_price(int model, double S, double K, double r, double q, double s
                      double E, int64_t T, int american, double lambda, double *price,
                      int64_t *boundary, double *margin)
 {
+    /* american: 1 American, 0 European; for the binomial call d >= 2 prices
+     * the Bermudan call exercisable every d steps back from expiry. */
+    if (american < 0 || (american > 1 && model != OR_BINOMIAL))
+        return OR_EINVAL;
     if (!price)
         return OR_EINVAL;
     if (!(isfinite(S) && isfinite(K) && isfinite(r) && isfinite(q) && isfinite(sigma) &&
@@ -474,7 +486,7 @@ int aop_oracle_price(int model, double S, double K, double r, double q, double s
         return OR_EINVAL;
     switch (model) {
     case OR_BINOMIAL:
-        return oracle_binomial(S, K, r, q, sigma, E, T, american, price, boundary, margin);
+        return oracle_binomial(S, K, r, q, sigma, E, T, (int64_t)american, price, boundary, margin);
     case OR_TRINOMIAL:
         return oracle_trinomial(S, K, r, q, sigma, E, T, american, price, boundary, margin);
     case OR_BSM_PUT:

@@ -348,3 +348,18 @@ def brute_bsm_put_boundary(S, K, r, sigma, E, T, lam=1.0 / 3.0):
     price = K * value(T, 0, math.log(S / K))
     bnd = _decisions_to_boundary(red_at, green_at, T, lambda n: 2 * T + 1, lattice=False)
     return price, [x - T if isinstance(x, int) else x for x in bnd]
+
+
+def brute_binomial_bermudan(S, K, r, q, sigma, E, T, every):
+    """Non-recombining binomial tree with exercise only at depths t (time
+    steps from today) where (T - t) % every == 0, t < T (and the payoff at T)."""
+    _, u, d, p, m = bopm_params(r, q, sigma, E, T)
+
+    def value(t, x):
+        ex = x - K
+        if t == T:
+            return max(ex, 0.0)
+        cont = m * (p * value(t + 1, x * u) + (1.0 - p) * value(t + 1, x * d))
+        return max(cont, ex) if (T - t) % every == 0 else cont
+
+    return value(0, S)

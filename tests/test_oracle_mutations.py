@@ -44,8 +44,9 @@ MUTATIONS = {
                                      "last = red ? j - 1 : last;\n            }\n        } else {\n            int prev_red = 1;"),
     "binomial_boundary_off_by_one_margin_path": ("                last = red ? j : last;\n                gap_last = red ? gap : gap_last;",
                                                  "                last = red ? j - 1 : last;\n                gap_last = red ? gap : gap_last;"),
-    "binomial_margin_of_wrong_cell": ("                gap_next = (!red && prev_red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : -1;\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)",
-                                      "                gap_next = (!red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : -1;\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)"),
+    "binomial_margin_of_wrong_cell": ("                gap_next = (!red && prev_red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : (every == 0 ? -1 : i);\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)",
+                                      "                gap_next = (!red) ? -gap : gap_next; /* the cell after a red one */\n                prev_red = red;\n            }\n        }\n        if (boundary) boundary[i] = american ? last : (every == 0 ? -1 : i);\n        if (margin && american) {\n            margin[2 * i] = last >= 0 ? gap_last : NAN;\n            margin[2 * i + 1] = (last + 1 <= i)"),
+    "bermudan_wrong_exercise_rows": ("(every > 1 && (T - i) % every == 0)", "(every > 1 && (T - i) % every == 1)"),
     "bsm_payoff_shift": ("double g = 1.0 - EX[k + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg",
                          "double g = 1.0 - EX[k + 1 + T];\n                int green = g > cont;\n                Vn[k + T] = green ? g : cont;\n                lastg"),
 }
@@ -98,6 +99,9 @@ def _battery(oracle_mod, lib):
                 b = P(2, 90.0, 110.0, 0.08, 0.0, 0.45, 2.0, T, **kw)[1]
                 if any(x != "tie" and int(b[i]) != (none if x is None else x) for i, x in enumerate(ref)):
                     fails.append("bsm boundary")
+        for T in (6, 9):
+            if abs(P(0, *prm, T, every=3) - pins.brute_binomial_bermudan(*prm, T, 3)) > 1e-12:
+                fails.append("bermudan brute force")
         # decision gaps at the boundary against a full numpy grid
         gp = (100.0, 95.0, 0.03, 0.05, 0.25, 1.0)
         T = 60

@@ -583,3 +583,65 @@ def test_gauss_window_covers_the_mass(oracle_mod):
         w = oracle_mod.european_gauss(oracle_mod.GAUSS_WINDOW, S, K, r, q, s, E, T)
         f = oracle_mod.european_gauss(oracle_mod.GAUSS_SUM, S, K, r, q, s, E, T)
         assert 0 <= f - w <= 1e-6 * f
+
+
+# ----------------------------------------------- Bermudan (discrete exercise)
+@pytest.mark.parametrize("every", [2, 3, 5])
+def test_bermudan_against_brute_force(oracle_mod, every):
+    prm = (120.0, 100.0, 0.08, 0.06, 0.3, 1.5)
+    for T in (5, 9, 12):
+        got = oracle_mod.price(B, *prm, T, every=every)
+        assert abs(got - pins.brute_binomial_bermudan(*prm, T, every)) <= 1e-12 * prm[1]
+
+
+def test_bermudan_limits_and_ordering(oracle_mod):
+    rng = np.random.default_rng([111, 0])
+    for _ in range(6):
+        p = inputs.draw_params(rng, B)
+        args = (p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], 600)
+        am = oracle_mod.price(B, *args)
+        eu = oracle_mod.price(B, *args, american=False)
+        assert oracle_mod.price(B, *args, every=1) == am
+        assert oracle_mod.price(B, *args, every=601) == eu
+        vals = [oracle_mod.price(B, *args, every=d) for d in (1, 2, 4, 8, 600)]
+        # nested exercise sets: more exercise dates never lower the value
+        assert all(vals[k] >= vals[k + 1] - 1e-12 * p["K"] for k in range(len(vals) - 1))
+        assert vals[-1] >= eu - 1e-12 * p["K"]
+
+
+def test_trinomial_is_bermudan_binomial_on_twice_the_steps(oracle_mod):
+    # Sec. 3's trinomial lattice with p_u = alpha^2, p_o = 2 alpha (1 - alpha),
+    # p_d = (1 - alpha)^2 is the binomial lattice of 2T steps with up
+    # probability alpha, exercisable every second row: same price, and the
+    # trinomial boundary of row i is the binomial boundary of row 2i.
+    rng = np.random.default_rng([112, 0])
+    for _ in range(5):
+        p = inputs.draw_params(rng, TR)
+        T = 300
+        args = (p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"])
+        pt, bt, mt = oracle_mod.price(TR, *args, T, boundary=True, margin=True)
+        pb, bb, mb = oracle_mod.price(B, *args, 2 * T, boundary=True, margin=True, every=2)
+        assert abs(pt - pb) <= 1e-11 * max(pt, 1e-3 * p["K"])
+        for i in range(T):
+            if bt[i] != bb[2 * i]:
+                assert _near_tie(mt, 2 * i) or _near_tie(mt, 2 * i + 1), (i, bt[i], bb[2 * i])
+
+
+@pytest.mark.parametrize("every", [2, 3, 8, 32])
+def test_bermudan_boundary_drops_at_most_one_column_per_row(oracle_mod, every):
+    # The reading the decomposition of a Bermudan call rests on: between two
+    # exercise rows i and i - d the boundary drops by at most d columns (one
+    # per row, as Corollary 2.6 gives on every row of the American lattice),
+    # so cells left of b_i - k stay continuation cells on row i - k.
+    rng = np.random.default_rng([113, every])
+    T = 1200
+    for _ in range(10):
+        p = inputs.draw_params(rng, B)
+        _, b, mg = oracle_mod.price(B, p["S0"], p["K"], p["r"], p["q"], p["sigma"], p["expiry"], T,
+                                    boundary=True, margin=True, every=every)
+        rows = [i for i in range(T - every, -1, -1) if (T - i) % every == 0]
+        for i_hi, i_lo in zip(rows, rows[1:]):
+            if b[i_hi] < 0 or b[i_hi] == i_hi:
+                continue
+            if b[i_lo] < b[i_hi] - every:
+                assert _near_tie(mg, 2 * i_lo) or _near_tie(mg, 2 * i_lo + 1)
