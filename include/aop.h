@@ -77,7 +77,15 @@ typedef enum {
  * below the expiry row, whose own entry is still reported. */
 #define AOP_EUROPEAN 1
 
-/* One option (host memory).  flags: 0 (American) or AOP_EUROPEAN. */
+/* One option (host memory).  flags: 0 (American) or AOP_EUROPEAN.
+ * exercise_every: 0 or 1 for the American (or, with AOP_EUROPEAN, European)
+ * option; d >= 2 for a Bermudan binomial call, exercisable only on the rows i
+ * with (T - i) % d == 0 -- every d time steps back from expiry (the paper's
+ * closing section lists Bermudan options as future work; here the same
+ * recursion steps from one exercise row to the next, so its cone widens by d
+ * columns per step).  d > T leaves no exercise before expiry.  Only
+ * AOP_BINOMIAL_CALL takes d >= 2 (others: AOP_ENOTIMPL); d >= 2 with
+ * AOP_EUROPEAN is AOP_EINVAL. */
 typedef struct {
     int32_t model;   /* aop_model */
     int32_t flags;
@@ -88,6 +96,7 @@ typedef struct {
     double sigma;    /* volatility per sqrt(year) */
     double expiry;   /* years */
     int64_t T;       /* time steps, 1 <= T <= AOP_MAX_T */
+    int64_t exercise_every; /* 0/1 every row; d >= 2 Bermudan (binomial) */
 } aop_option;
 
 typedef struct aop_ctx aop_ctx;

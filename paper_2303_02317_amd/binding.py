@@ -73,7 +73,8 @@ SERVER_STATS = ["submitted", "completed", "batches", "inflight", "pending", "pea
 class AopOption(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("flags", ctypes.c_int32), ("S0", ctypes.c_double),
                 ("K", ctypes.c_double), ("r", ctypes.c_double), ("q", ctypes.c_double),
-                ("sigma", ctypes.c_double), ("expiry", ctypes.c_double), ("T", ctypes.c_int64)]
+                ("sigma", ctypes.c_double), ("expiry", ctypes.c_double), ("T", ctypes.c_int64),
+                ("exercise_every", ctypes.c_int64)]
 
 
 _lib = None
@@ -138,7 +139,7 @@ def options_array(opts) -> ctypes.Array:
     for i, o in enumerate(opts):
         flags = AOP_EUROPEAN if o.get("european", False) else 0
         arr[i] = AopOption(int(o["model"]), flags, float(o["S0"]), float(o["K"]), float(o["r"]), float(o["q"]),
-                           float(o["sigma"]), float(o["expiry"]), int(o["T"]))
+                           float(o["sigma"]), float(o["expiry"]), int(o["T"]), int(o.get("exercise_every", 0)))
     return arr
 
 

@@ -42,6 +42,8 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         (o.flags & ~AOP_EUROPEAN) != 0)
         return AOP_EINVAL;
     const bool european = (o.flags & AOP_EUROPEAN) != 0;
+    if (o.exercise_every < 0 || (european && o.exercise_every > 1)) return AOP_EINVAL;
+    if (o.exercise_every > 1 && o.model != AOP_BINOMIAL_CALL) return AOP_ENOTIMPL;
     if (o.T > AOP_MAX_T) return AOP_ETOOBIG;
     const double T = (double)o.T;
     d.T = o.T;
@@ -85,7 +87,7 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         // R < 0 and no dividend a row's top cell can exercise under an
         // all-continuation row, a drop of three or more columns, so the
         // decomposition does not apply.
-        if (o.r < 0.0 && !european) return AOP_EPROB;
+        if (o.r < 0.0 && !european) return AOP_EPROB;  // (American trinomial only)
         d.a = A;
         d.no_green = (o.q == 0.0 && o.r >= 0.0);  // as for the binomial lattice
         d.w0 = m * pd;
@@ -116,7 +118,7 @@ aop_status make_desc(const aop_option &o, double lambda, Desc &d)
         return AOP_EINVAL;
     }
     d.model = o.model;
-    d.european = european ? 1 : 0;
+    d.ex_every = european ? 0 : (o.exercise_every > 1 ? (int32_t)std::min<int64_t>(o.exercise_every, o.T + 1) : 1);
     return AOP_OK;
 }
 

@@ -542,8 +542,9 @@ aop_status make_opt(const aop_option &o, double lambda, Opt &d)
           std::isfinite(o.sigma) && std::isfinite(o.expiry)))
         return AOP_EINVAL;
     if (o.S0 <= 0 || o.K <= 0 || o.sigma <= 0 || o.expiry <= 0 || o.q < 0 || o.T < 1 ||
-        (o.flags & ~AOP_EUROPEAN) != 0)
+        (o.flags & ~AOP_EUROPEAN) != 0 || o.exercise_every < 0)
         return AOP_EINVAL;
+    if (o.exercise_every > 1) return AOP_ENOTIMPL;  // Bermudan exercise: the GPU library only
     if (o.T > AOP_MAX_T) return AOP_ETOOBIG;
     d = Opt{};
     d.model = o.model;

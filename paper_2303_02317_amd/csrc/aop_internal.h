@@ -33,10 +33,20 @@ struct Desc {
     int64_t nfft;       // complex elements in the FFT scratch
     int64_t out_index;  // index of this option in the caller's arrays
     int32_t no_green;   // lattice call with Y = 0, R >= 0: no exercise cell below the expiry row (Lemma 2.3)
-    int32_t european;   // exercise only at expiry: the root is one correlation of the expiry row
+    int32_t ex_every;   // exercise rows: 1 every row (American), 0 none before expiry (European),
+                        // d >= 2 the rows i with (T - i) % d == 0 (Bermudan, binomial call only)
     int64_t scr_len;    // complex elements of FFT scratch (a stack shared by the outstanding correlations)
 };
 static_assert(sizeof(Desc) == 128, "descriptor is 128 bytes");
+
+// Whether row i (lattices; step T - i) of an option may exercise.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline bool exercise_row(const Desc &d, int64_t i)
+{
+    return d.ex_every == 1 || (d.ex_every > 1 && (d.T - i) % d.ex_every == 0);
+}
 
 // Per-option work counters (mirror of aop_stats), stored after the descriptors.
 struct Stats {

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__rest
                 nx[PL_C - 2] = d.w0 * g[PL_C - 2] + d.w1 * g[PL_C - 1] + d.w2 * n0;
                 nx[PL_C - 1] = d.w0 * g[PL_C - 1] + d.w1 * n0 + d.w2 * n1;
             }
+            const bool ex = exercise_row(d, itop - k);  // uniform
             if (BND) {
                 ll last = LLONG_MIN;
                 const ll irow = itop - k;
@@ -135,19 +136,19 @@ __global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__rest
                 for (int c = 0; c < PL_C; ++c) {
                     x[c] *= u;  // S u^{col - i} one row lower
                     const double e = x[c] - d.K;
-                    const bool red = d.european || pl_red(nx[c], e);
+                    const bool red = !ex || pl_red(nx[c], e);
                     g[c] = red ? nx[c] : e;
                     // a cell is exact where its cone stayed inside the tile
                     const ll loc = lane * PL_C + c;
                     if (red && loc < PL_W - span * k && j0 + loc <= (bin ? irow : 2 * irow)) last = j0 + loc;
                 }
-                if (!d.european) note_boundary(bnd + irow, last);
+                if (d.ex_every != 0) note_boundary(bnd + irow, ex ? last : (bin ? irow : 2 * irow));
             } else {
 #pragma unroll
                 for (int c = 0; c < PL_C; ++c) {
                     x[c] *= u;  // S u^{col - i} one row lower
                     const double e = x[c] - d.K;
-                    g[c] = (d.european || pl_red(nx[c], e)) ? nx[c] : e;
+                    g[c] = (!ex || pl_red(nx[c], e)) ? nx[c] : e;
                 }
             }
         }
@@ -200,16 +201,16 @@ __global__ void __launch_bounds__(64 * PL_WAVES) plain_kernel(const Desc *__rest
                 const ll hw = T - n - k;  // cone of step n + k: |cell| <= hw
 #pragma unroll
                 for (int c = 0; c < PL_C; ++c) {
-                    const bool green = !d.european && x[c] > nx[c];
+                    const bool green = d.ex_every != 0 && x[c] > nx[c];
                     g[c] = green ? x[c] : nx[c];
                     const ll loc = lane * PL_C + c;
                     const ll kk = kb + loc;
                     if (green && loc >= k && loc < PL_W - k && kk >= -hw && kk <= hw) last = kk;
                 }
-                if (!d.european) note_boundary(bnd + n + k, last);
+                if (d.ex_every != 0) note_boundary(bnd + n + k, last);
             } else {
 #pragma unroll
-                for (int c = 0; c < PL_C; ++c) g[c] = (!d.european && x[c] > nx[c]) ? x[c] : nx[c];
+                for (int c = 0; c < PL_C; ++c) g[c] = (d.ex_every != 0 && x[c] > nx[c]) ? x[c] : nx[c];
             }
         }
         const ll hi_out = T - n - r;

@@ -41,7 +41,7 @@ typedef long long ll;
 
 // Model parameters, passed by value so that they live in registers.
 struct Mp {
-    int model, no_green, european;
+    int model, no_green, ex_every;  // ex_every: 1 American, 0 European, d >= 2 Bermudan (rows (T - i) % d == 0)
     ll T;
     double S, K, a, s0, w0, w1, w2;
 };
@@ -51,7 +51,7 @@ __device__ __forceinline__ Mp make_mp(const Desc &d)
     p.model = d.model;
     p.T = d.T;
     p.no_green = d.no_green;
-    p.european = d.european;
+    p.ex_every = d.ex_every;
     p.S = d.S;
     p.K = d.K;
     p.a = d.a;
@@ -1223,9 +1223,62 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
     return bc;
 }
 
+// Band of a Bermudan binomial call (exercise on the rows i with (T - i) % d
+// == 0, d = p.ex_every >= 2): rows i0-1 .. i0-h from the exercise row i0,
+// whose red cells are [c0, b].  On the other rows every cell is a
+// continuation cell (the linear stencil only).  The cells beyond the band,
+// right of the boundary of the exercise row above, are exercise cells there,
+// so on the rows below their values are the n-step linear stencil applied to
+// exercise values: S u^{2j-i} rho_S^n - K rho_K^n (the forward identity of the
+// lattice), with rho_S = w_up u + w_dn / u, rho_K = w_dn + w_up and n the rows
+// since that exercise row.  The boundary of an exercise row is its last red
+// cell (the ballot's highest lane); the other rows report their last column.
+// Returns the boundary of row i0-h (an exercise row for trapezoid leaves).
+__device__ __noinline__ ll band_bermudan(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
+                                         ll *bnd, double *v0)
+{
+    const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
+    const int T = (int)p.T, ev = p.ex_every;
+    const int l = threadIdx.x & 63;
+    const int j = c0 + l;
+    const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1;
+    const double u = exp(a);
+    const double ku = K * (u - 1.0);
+    const double lrs = log(w1 * u + w0 / u), lrk = log(w0 + w1);
+    double g = (j <= b) ? src[j] : ((j <= i0) ? S * exp((double)(2 * j - i0) * a) - K : 0.0);
+    double e = 0.0;
+    // the fill: value of column c0 + 64 in the row being read
+    double f1 = S * exp((double)(2 * (c0 + BAND) - i0) * a) - K;
+    int bc = b;
+    const int reseed = (a * 64.0 <= 4.0) ? 64 : max(1, (int)(4.0 / a));
+    for (int k = 1; k <= h; ++k) {
+        const int i = i0 - k;
+        if ((k - 1) % reseed == 0) e = S * exp((double)(2 * j - (i + 1)) * a) - K;  // row i+1, then advanced
+        const double g1 = dpp_dn1(g, f1);
+        const double c = fma(w1, g1, w0 * g);
+        e = fma(e, u, ku);
+        const int n = (T - i) % ev;  // rows since the exercise row above (0: row i exercises)
+        if (n == 0) {
+            const bool red = (c >= e) && (c < INFINITY);
+            g = red ? c : e;
+            const unsigned long long m = __ballot(red) & row_mask(i - c0);
+            bc = m ? c0 + 63 - (int)__clzll(m) : c0 - 1;
+            if (bnd && l == 0) bnd[i] = bc;
+        } else {
+            g = c;
+            if (bnd && l == 0) bnd[i] = i;
+        }
+        f1 = S * exp((double)(2 * (c0 + BAND) - i) * a + (double)n * lrs) - K * exp((double)n * lrk);
+    }
+    if (j <= bc) dst[j] = g;
+    if (v0 && l == 0) *v0 = g;
+    return bc;
+}
+
 __device__ __forceinline__ ll band_bin(Mp p, ll i0, ll c0, ll h, ll b, const double *src, double *dst, ll *bnd,
                                        double *v0)
 {
+    if (p.ex_every > 1) return band_bermudan(p, i0, c0, h, b, src, dst, bnd, v0);
     return band_lat<false>(p, i0, c0, h, b, src, dst, bnd, v0);
 }
 __device__ __forceinline__ ll band_tri(Mp p, ll i0, ll c0, ll h, ll b, const double *src, double *dst, ll *bnd,
@@ -2086,7 +2139,10 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
 {
     const Mp d = cx.p;
     const int l = threadIdx.x & 63;
-    const int span = (d.model == BINOMIAL) ? 1 : 2;
+    // a lattice frame steps kstep rows at a time (a Bermudan binomial call: from
+    // one exercise row to the next) and its cone widens by span columns per step
+    const ll kstep = (d.model == BINOMIAL && d.ex_every > 1) ? d.ex_every : 1;
+    const ll span = (d.model == BINOMIAL) ? kstep : 2;
     const ll timeout = cx.tn.timeout_ticks;
     if (cap > WQ) cap = WQ;  // one outstanding correlation per frame fits the queue
     // The frame being worked on (depth sp) lives in registers; the stack
@@ -2100,11 +2156,11 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     auto walk = [&](const Frame &f) -> ll {
         const ll tb = clk();
         ll r;
-        if (d.model == BINOMIAL) r = band_bin(d, f.r0, f.c0, f.h, f.b, f.src, f.dst, cx.bnd, nullptr);
+        if (d.model == BINOMIAL) r = band_bin(d, f.r0, f.c0, kstep * f.h, f.b, f.src, f.dst, cx.bnd, nullptr);
         else if (d.model == TRINOMIAL) r = band_tri(d, f.r0, f.c0, f.h, f.b, f.src, f.dst, cx.bnd, nullptr);
         else r = band_bsm(d, f.r0, f.c0, f.h, f.c0 + 2 * f.h, f.src, f.dst, cx.bnd, nullptr);
         if (l == 0) {
-            b_rows += f.h;
+            b_rows += kstep * f.h;
             b_cyc += clk() - tb;
         }
         return uni(r);
@@ -2149,8 +2205,8 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
                     else {
                         csrc = fr.src + c0;
                         cn = nred;
-                        ch = h1;
-                        coff = (span == 1) ? 0 : h1;
+                        ch = kstep * h1;
+                        coff = (d.model == BINOMIAL) ? 0 : h1;
                         cout = nred - span * h1;
                         cdst = mid + c0;
                         fr.mid = mid;
@@ -2165,13 +2221,13 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
                 else {
                     csrc = fr.mid + c0;
                     cn = n2;
-                    ch = h2;
-                    coff = (span == 1) ? 0 : h2;
+                    ch = kstep * h2;
+                    coff = (d.model == BINOMIAL) ? 0 : h2;
                     cout = n2 - span * h2;
                     cdst = fr.dst + c0;
                     fr.stage = 2;
-                    child = Frame{i0 - h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst, nullptr,
-                                  0, 0};
+                    child = Frame{i0 - kstep * h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst,
+                                  nullptr, 0, 0};
                 }
             } else {
                 pop = true;  // rv: the second sub-trapezoid's boundary
@@ -2294,11 +2350,14 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
 // then takes the frame one stage further, which may submit one correlation.
 template <int PREC>
 __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *stk, int *sp_sh, ll *ret_sh,
-                                              ll *leaf_sh)
+                                              ll *leaf_sh, ll *red_sh)
 {
     const Mp d = cx.p;
     const int tid = threadIdx.x;
-    const int span = (d.model == BINOMIAL) ? 1 : 2;  // columns consumed per row (lattices)
+    // lattice frames step kstep rows at a time (a Bermudan binomial call: from
+    // one exercise row to the next); the cone widens by span columns per step
+    const ll kstep = (d.model == BINOMIAL && d.ex_every > 1) ? d.ex_every : 1;
+    const ll span = (d.model == BINOMIAL) ? kstep : 2;
     if (tid == 0) {
         stk[0] = root;
         *sp_sh = 0;
@@ -2338,9 +2397,55 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll h1 = h / 2, h2 = h - h1;
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
-                if (nred <= BAND || wave_sized(d, cx.tn, nred, h)) {
+                if (nred <= BAND || (kstep <= BAND && wave_sized(d, cx.tn, nred, kstep * h))) {
                     leaf = true;  // wave 0 solves it alone (band, or direct steps and bands)
                     pop = true;
+                } else if (kstep > 1 && h == 1) {
+                    // One exercise interval of a Bermudan call over more red
+                    // cells than a band holds (kstep > BAND): the cells right
+                    // of b are exercise cells of row i0, so the red cells
+                    // extended by their exercise values are correlated over
+                    // kstep rows in one piece, then the max is taken on the
+                    // exercise row below.
+                    const ll wext = (b + kstep < i0) ? b + kstep : i0;  // last column read on row i0
+                    const ll n_in = wext - c0 + 1, n_out = n_in - kstep, i1 = i0 - kstep;
+                    double *ext = cx.arena + fr.aoff;
+                    if (n_out < 1) {
+                        // row i1 ends left of c0: its cells are all continuation
+                        // cells of the parent's left part, and its boundary is its end
+                        if (cx.bnd)
+                            for (ll i = i1 + tid; i < i0; i += WG) cx.bnd[i] = i;
+                        result = i1;
+                        pop = true;
+                    } else if (fr.aoff + n_in > cx.arena_len || slot >= JPW) e = DEV_ARENA;
+                    else if (!in_ws(cx, fr.src, c0, b) || !in_ws(cx, fr.dst, c0, c0 + n_out - 1))
+                        e = DEV_RANGE;
+                    else {
+                        for (ll k = tid; k < n_in; k += WG)
+                            ext[k] = (c0 + k <= b) ? fr.src[c0 + k] : ex_bin(d, i0, c0 + k);
+                        __syncthreads();
+                        // tilted about the strike column (the exercise values grow like u^{2j})
+                        double tc = 0.5 * ((double)i0 + log(d.K / d.S) / d.a) - (double)c0;
+                        tc = tc < 0.0 ? 0.0 : (tc > (double)(n_in - 1) ? (double)(n_in - 1) : tc);
+                        conv_submit<PREC>(cx, slot, fr.soff, ext, n_in, kstep, 0, n_out, fr.dst + c0, 2.0 * d.a, tc);
+                        conv_wait<PREC>(cx, slot);
+                        ll last = c0 - 1;
+                        for (ll k = tid; k < n_out; k += WG) {
+                            const ll j = c0 + k;
+                            const double c = fr.dst[j], ee = ex_bin(d, i1, j);
+                            const bool red = red_of(c, ee);
+                            fr.dst[j] = red ? c : ee;
+                            if (red && j > last) last = j;
+                        }
+                        last = block_max(last, red_sh);
+                        if (cx.bnd) {
+                            for (ll i = i1 + 1 + tid; i < i0; i += WG) cx.bnd[i] = i;  // rows without exercise
+                            if (tid == 0) cx.bnd[i1] = last;
+                        }
+                        if (tid == 0) cx.st->band_rows += kstep;
+                        result = last;
+                        pop = true;
+                    }
                 } else {
                     // (1) row r = i0 - h1, columns [c0, b - span h1], by correlation from row i0.
                     double *mid = cx.arena + fr.aoff - c0;
@@ -2349,8 +2454,8 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                     else {
                         csrc = fr.src + c0;
                         cn = nred;
-                        ch = h1;
-                        coff = (span == 1) ? 0 : h1;
+                        ch = kstep * h1;
+                        coff = (d.model == BINOMIAL) ? 0 : h1;
                         cout = nred - span * h1;
                         cdst = mid + c0;
                         fr.mid = mid;
@@ -2367,14 +2472,14 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                 else {
                     csrc = fr.mid + c0;
                     cn = n2;
-                    ch = h2;
-                    coff = (span == 1) ? 0 : h2;
+                    ch = kstep * h2;
+                    coff = (d.model == BINOMIAL) ? 0 : h2;
                     cout = n2 - span * h2;
                     cdst = fr.dst + c0;
                     fr.stage = 2;
                     // (4) sub-trapezoid on the last span*h2 red cells of row r
-                    child = Frame{i0 - h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst, nullptr,
-                                  0, 0};
+                    child = Frame{i0 - kstep * h1, br - span * h2 + 1, h2, br, fr.aoff + nred, 0, fr.mid, fr.dst,
+                                  nullptr, 0, 0};
                 }
             } else {
                 result = rv;
@@ -2491,6 +2596,8 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
     const int tid = threadIdx.x;
     const bool bin = d.model == BINOMIAL;
     const ll wT = bin ? T : 2 * T;  // last column of row T
+    const int ev = d.ex_every;      // 1 American, 0 European, >= 2 Bermudan (binomial)
+    const bool berm = ev > 1;
     // Expiry row T (red = out of the money: G^red = 0 >= G^green) and row T-1.
     const ll tr0 = clk();
     ll lastT = -1, lastT1 = -1;
@@ -2510,7 +2617,8 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
                 c = d.w0 * g0 + d.w1 * g1 + d.w2 * g2;
             }
             const double e = bin ? ex_bin(d, T - 1, j) : ex_tri(d, T - 1, j);
-            const bool red = d.european || red_of(c, e);  // European: no exercise before expiry
+            // European or Bermudan: row T-1 has no exercise
+            const bool red = ev != 1 || red_of(c, e);
             rowA[j] = red ? c : e;
             if (red) lastT1 = j;
         }
@@ -2520,12 +2628,17 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
     lastT1 = block_max(lastT1, red_sh);
     if (cx.bnd && tid == 0) {
         cx.bnd[T] = lastT;
-        cx.bnd[T - 1] = d.european ? -1 : lastT1;
+        cx.bnd[T - 1] = ev == 0 ? -1 : lastT1;
     }
     if (tid == 0) cx.st->cyc_rows += clk() - tr0;
     ll i0 = T - 1, b = lastT1;
     double *src = rowA, *dst = rowB;
-    if (T > 1 && (d.no_green || d.european || b == wT - (bin ? 1 : 2))) {
+    // strike column of row i (binomial), the centre of a tilted correlation
+    auto strike_col = [&](ll i, ll last) {
+        double tc = 0.5 * ((double)i + log(d.K / d.S) / d.a);
+        return tc < 0.0 ? 0.0 : (tc > (double)last ? (double)last : tc);
+    };
+    if (T > 1 && (d.no_green || ev == 0 || (berm && ev > T) || (ev == 1 && b == wT - (bin ? 1 : 2)))) {
         // No exercise cell below the expiry row: with Y = 0 Lemma 2.3 leaves
         // none (the classification of far in-the-money cells of row T-1 is
         // then rounding noise), and an entirely red row T-1 keeps every row
@@ -2534,16 +2647,17 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         // linear functional of row T-1, whose values grow like S u^{col}, so
         // the correlation is tilted about the at-the-money column tc.  A
         // European option (exercise at expiry only) takes the same single
-        // correlation: row T-1 was computed without exercise.
+        // correlation: row T-1 was computed without exercise; so does a
+        // Bermudan option with no exercise row below the expiry row.
         b = wT - (bin ? 1 : 2);
-        if (cx.bnd && tid == 0) cx.bnd[T - 1] = d.european ? -1 : b;
+        if (cx.bnd && tid == 0) cx.bnd[T - 1] = ev == 0 ? -1 : b;
         const double beta = bin ? 2.0 * d.a : d.a;
         double tc = bin ? 0.5 * ((double)(T - 1) + log(d.K / d.S) / d.a)
                         : (double)(T - 1) + log(d.K / d.S) / d.a;
         if (tc < 0.0) tc = 0.0;
         if (tc > (double)b) tc = (double)b;
         if (cx.bnd)
-            for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = d.european ? -1 : (bin ? i : 2 * i);
+            for (ll i = tid; i < T - 1; i += WG) cx.bnd[i] = ev == 0 ? -1 : (bin ? i : 2 * i);
         const ll hh = T - 1;
         conv_submit<PREC>(cx, SLOT_TOP, 0, src, b + 1, hh, bin ? 0 : hh, 1, dst, beta, tc);
         conv_wait<PREC>(cx, SLOT_TOP);
@@ -2551,12 +2665,60 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
         __syncthreads();
         return *val_sh;
     }
+    // Bermudan binomial call: the rows between exercise rows carry no
+    // exercise, so the recursion steps from one exercise row to the next (ev
+    // rows, whose kernel is the ev-step binomial one; the cone widens by ev
+    // columns per step).  The first exercise row below expiry, i1 = T - ev,
+    // is computed directly: row T-1 (linear) correlated over ev - 1 rows,
+    // tilted like the Y = 0 case (the row is linear up to its top), then the
+    // max with the exercise values.
+    const ll r0 = berm ? T % ev : 0;  // lowest exercise row
+    // The exercise row i0 (red cells [0, b] in src) stepped to row tgt = i0 - s
+    // through the whole row: the cells right of b are exercise cells, whose
+    // values enter; then, if tgt exercises, the max and the boundary.
+    auto full_step = [&](ll s, double *from, double *to) -> ll {
+        for (ll j = b + 1 + tid; j <= i0; j += WG) from[j] = ex_bin(d, i0, j);
+        __syncthreads();
+        const ll tgt = i0 - s;
+        conv_submit<PREC>(cx, SLOT_TOP, 0, from, i0 + 1, s, 0, tgt + 1, to, 2.0 * d.a, strike_col(i0, i0));
+        conv_wait<PREC>(cx, SLOT_TOP);
+        ll last = -1;
+        const bool exr = (T - tgt) % ev == 0;
+        for (ll j = tid; j <= tgt; j += WG) {
+            const double c = to[j], e = ex_bin(d, tgt, j);
+            const bool red = !exr || red_of(c, e);
+            to[j] = red ? c : e;
+            if (red) last = j;
+        }
+        last = block_max(last, red_sh);
+        if (cx.bnd) {
+            for (ll i = tgt + 1 + tid; i < i0; i += WG) cx.bnd[i] = i;  // rows without exercise
+            if (tid == 0) cx.bnd[tgt] = exr ? last : tgt;
+        }
+        if (tid == 0) cx.st->direct_cells += tgt + 1;
+        __syncthreads();
+        return last;
+    };
+    if (berm) {
+        b = full_step(ev - 1, src, dst);  // i0 = T - 1: rows T-1 .. T-ev+1 have no exercise
+        i0 = T - ev;
+        double *t = src;
+        src = dst;
+        dst = t;
+        if (*cx.err_sh) return NAN;
+    }
     while (i0 > 0) {
-        if (b < 0) {  // no red cell: every row below is green (Lemma 2.4)
+        if (b < 0) {
+            // no red cell: every exercise row below is green (Lemma 2.4).  A
+            // Bermudan option's rows without exercise continue linearly from
+            // exercise values, down to the root from the lowest exercise row
+            // r0: S u^{2j-i} rho_S^n - K rho_K^n at n = r0 rows below it.
             if (cx.bnd)
-                for (ll i = tid; i < i0; i += WG) cx.bnd[i] = -1;
+                for (ll i = tid; i < i0; i += WG) cx.bnd[i] = (berm && (T - i) % ev != 0) ? i : -1;
             __syncthreads();
-            return d.S - d.K;
+            if (!berm || r0 == 0) return d.S - d.K;
+            const double u = exp(d.a);
+            return d.S * exp((double)r0 * log(d.w1 * u + d.w0 / u)) - d.K * exp((double)r0 * log(d.w0 + d.w1));
         }
         const ll nred = b + 1;
         if (nred <= BAND) {  // the band walks the leftover triangle to the root
@@ -2572,13 +2734,39 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
             }
             return *val_sh;
         }
-        ll h = bin ? nred : nred / 2;
-        if (h > i0) h = i0;
+        ll h, rows;
+        if (berm) {
+            // trapezoid height in exercise intervals, down to the lowest exercise row
+            h = nred / ev;
+            if (h > (i0 - r0) / ev) h = (i0 - r0) / ev;
+            if (h == 0) {
+                // the red cells are fewer than one interval, or the lowest
+                // exercise row is reached: step through the whole row
+                const ll s = (i0 == r0) ? i0 : ev;
+                b = full_step(s, src, dst);
+                if (*cx.err_sh) return NAN;
+                i0 -= s;
+                double *t = src;
+                src = dst;
+                dst = t;
+                if (i0 == 0 && (T % ev) != 0) {  // the root is on a row without exercise
+                    if (tid == 0) *val_sh = read_result(src);
+                    __syncthreads();
+                    return *val_sh;
+                }
+                continue;
+            }
+            rows = ev * h;
+        } else {
+            h = bin ? nred : nred / 2;
+            if (h > i0) h = i0;
+            rows = h;
+        }
         Frame root{i0, 0, h, b, 0, 0, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        b = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        b = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh, red_sh);
         if (*cx.err_sh) return NAN;
-        i0 -= h;
+        i0 -= rows;
         double *t = src;
         src = dst;
         dst = t;
@@ -2607,7 +2795,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
             const double gm = ex_bsm(d, k - 1), gp = ex_bsm(d, k + 1);
             const double cont = d.w0 * (gm > 0.0 ? gm : 0.0) + d.w1 * (g > 0.0 ? g : 0.0) +
                                  d.w2 * (gp > 0.0 ? gp : 0.0);
-            const bool green = !d.european && g > cont;  // European: exercise at expiry only
+            const bool green = d.ex_every != 0 && g > cont;  // European: exercise at expiry only
             A[k] = green ? g : cont;
             if (green) f1 = k;
         }
@@ -2663,7 +2851,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
         const ll need = conv_submit<PREC>(cx, SLOT_TOP, 0, src + f + 1, w, h, h, w - 2 * h, dst + f + 1 + h);
         Frame root{n, f, h, 0, 0, need, src, dst, nullptr, 0, 0};
         if (tid == 0) cx.st->trapezoids += 1;
-        const ll fn = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh);
+        const ll fn = solve_trapezoid<PREC>(cx, root, stk, sp_sh, ret_sh, leaf_sh, red_sh);
         conv_wait<PREC>(cx, SLOT_TOP);
         if (*cx.err_sh) return NAN;
         n += h;
