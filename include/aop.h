@@ -310,6 +310,9 @@ typedef struct {
     int32_t late_pub_min_lg; /* once late_after_pct % of the launch's options are done, the drivers
                                 still running publish FFT correlations of size >= 2^this (0 = never) */
     int32_t late_after_pct;  /* 0..100 */
+    int32_t lds_max_lg;     /* FP64 correlations of up to 2^this points run as one LDS transform,
+                               longer ones as four-step transforms of 2048-point rows (11 or 12) */
+    int32_t radix_lg;       /* FP64 LDS butterfly passes of radix 2^radix_lg (2 or 3) */
     int64_t timeout_ms;     /* a wait longer than this aborts the launch: its options price NaN (> 0) */
 } aop_tuning;
 aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out);

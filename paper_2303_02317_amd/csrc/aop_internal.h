@@ -95,6 +95,8 @@ struct Tune {
     int32_t prec;          // precision of the batch (every descriptor's): 0 FP64, 1 split-FP32 FFT
     int32_t late_pub_lg;   // publication threshold once late_after options are done (0: never)
     int32_t late_after;    // options done (set per launch from the percentage)
+    int32_t lds_lg64;      // FP64 transforms of up to 2^lds_lg64 points run whole in LDS (11 or 12)
+    int32_t radix;         // FP64 LDS butterfly passes of radix 2^radix (2 or 3)
     int64_t timeout_ticks; // wall-clock ticks a wait may take before the launch aborts
     int64_t idle_ticks;    // wall-clock ticks a helper waits for work before it leaves
 };

@@ -145,9 +145,15 @@ __device__ ll block_max(ll v, ll *sh)
 // Inverse (unnormalised): decimation in time, bit-reversed in -> natural out.
 // Each pass loads 2^K elements per lane, applies K radix-2 stages in
 // registers and stores them back, so a 2048-point transform takes four LDS
-// round trips.  twl holds e^{-2 pi i t / 4096}, t <= 2048 (LDS).
+// round trips.  twl holds e^{-2 pi i t / 4096}, t <= 2048 (LDS); both are
+// addressed through px().
 // w * e^{-2 pi i p / 2^(t+1)}, p < 2^t <= 4: one of the 8th roots of unity
 // (t and p are constants after unrolling, so this folds to a few operations).
+// Index into the LDS transform buffer and trig table: one padding element
+// after every 8 complex values, so that the strided passes of a transform
+// (stride 8 .. 64 elements at the last stages) fall on different banks.
+__device__ __forceinline__ int px(int i) { return i + (i >> 3); }
+
 __device__ __forceinline__ double2 rot_root(double2 w, int t, int p)
 {
     if (p == 0) return w;
@@ -177,9 +183,9 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
         const int base = b * n + (blk << (s_hi + 1)) + j;
         double2 v[G], om[K];
 #pragma unroll
-        for (int q = 0; q < G; ++q) v[q] = x[base + (q << s_lo)];
+        for (int q = 0; q < G; ++q) v[q] = x[px(base + (q << s_lo))];
 #pragma unroll
-        for (int t = 0; t < K; ++t) om[t] = twl[j << (11 - s_lo - t)];
+        for (int t = 0; t < K; ++t) om[t] = twl[px(j << (11 - s_lo - t))];
         if (!INV) {
 #pragma unroll
             for (int t = K - 1; t >= 0; --t) {
@@ -206,16 +212,16 @@ __device__ __forceinline__ void lds_pass(double2 *x, int lg, int nb, int s_lo, c
             }
         }
 #pragma unroll
-        for (int q = 0; q < G; ++q) x[base + (q << s_lo)] = v[q];
+        for (int q = 0; q < G; ++q) x[px(base + (q << s_lo))] = v[q];
     }
     __syncthreads();
 }
 
-__device__ void lds_dif(double2 *x, int lg, int nb, const double2 *twl)
+__device__ void lds_dif(double2 *x, int lg, int nb, const double2 *twl, int rk)
 {
     int s_hi = lg - 1;
     while (s_hi >= 0) {
-        const int k = s_hi + 1 >= 3 ? 3 : s_hi + 1;
+        const int k = s_hi + 1 >= rk ? rk : s_hi + 1;
         const int s_lo = s_hi - k + 1;
         if (k == 3) lds_pass<3, false>(x, lg, nb, s_lo, twl);
         else if (k == 2) lds_pass<2, false>(x, lg, nb, s_lo, twl);
@@ -224,11 +230,11 @@ __device__ void lds_dif(double2 *x, int lg, int nb, const double2 *twl)
     }
 }
 
-__device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl)
+__device__ void lds_dit_inv(double2 *x, int lg, int nb, const double2 *twl, int rk)
 {
     int s_lo = 0;
     while (s_lo < lg) {
-        const int k = lg - s_lo >= 3 ? 3 : lg - s_lo;
+        const int k = lg - s_lo >= rk ? rk : lg - s_lo;
         if (k == 3) lds_pass<3, true>(x, lg, nb, s_lo, twl);
         else if (k == 2) lds_pass<2, true>(x, lg, nb, s_lo, twl);
         else lds_pass<1, true>(x, lg, nb, s_lo, twl);
@@ -458,8 +464,8 @@ __device__ __forceinline__ Spec make_spec(const Mp &p, ll h, double beta, double
 // Trig values of a bin from the LDS table (e^{-2 pi i t / 4096}, t <= 2048).
 __device__ __forceinline__ double2 twl_at(const double2 *twl, int t)  // any t in [0, 4096)
 {
-    if (t <= 2048) return twl[t];
-    const double2 w = twl[t - 2048];  // e^{-i pi} e^{-2 pi i (t - 2048) / 4096}
+    if (t <= 2048) return twl[px(t)];
+    const double2 w = twl[px(t - 2048)];  // e^{-i pi} e^{-2 pi i (t - 2048) / 4096}
     return make_double2(-w.x, -w.y);
 }
 // Largest transform (log2 of its points) that runs whole in LDS.
@@ -468,11 +474,11 @@ __device__ __forceinline__ int lds_lg(int prec) { return prec ? LG_NLDS : LG_NLD
 // Bin f of a transform of 2^lgN <= 4096 points: theta = 2 pi f / N, f <= N / 2.
 __device__ __forceinline__ void bin_trig_lds(const double2 *twl, ll f, int lgN, double &cs, double &sn, double &sh)
 {
-    const double2 e = twl[f << (12 - lgN)];
+    const double2 e = twl[px((int)(f << (12 - lgN)))];
     cs = e.x;
     sn = -e.y;
     if (lgN <= LG_NLDS) {
-        sh = twl[f << (11 - lgN)].y;
+        sh = twl[px((int)(f << (11 - lgN)))].y;
     } else {  // 4096 points: theta / 2 is not on the table's grid
         double c2;
         sincospi((double)f / (double)(ll(1) << lgN), &sh, &c2);
@@ -487,7 +493,7 @@ __device__ __forceinline__ void bin_trig_rows(const double2 *twl, double2 r1, do
     const double2 e = cmul(r1, a);
     cs = e.x;
     sn = -e.y;
-    sh = cmul(r2, twl[k2]).y;
+    sh = cmul(r2, twl[px(k2)]).y;
 }
 // e^{-2 pi i m / N}, m < N (four-step column twiddles), by sincospi in FP64.
 __device__ __forceinline__ double2 twiddle_n(ll m, int lgN)
@@ -567,8 +573,9 @@ struct JobArgs {
     ll n_in, h, out_off, n_out;
     double beta, tc;
     int desc, lgN, kind, ntile, nph, prec;  // prec: 0 FP64, 1 split FP32
+    int radix, pad;                          // FP64 LDS passes of radix 2^radix (2 or 3)
 };
-static_assert(sizeof(JobArgs) == 96, "job arguments are 96 bytes");
+static_assert(sizeof(JobArgs) == 104, "job arguments are 104 bytes");
 
 __device__ __forceinline__ JobArgs uni_args(JobArgs a)
 {
@@ -583,6 +590,7 @@ __device__ __forceinline__ JobArgs uni_args(JobArgs a)
     u.ntile = __builtin_amdgcn_readfirstlane(a.ntile);
     u.nph = __builtin_amdgcn_readfirstlane(a.nph);
     u.prec = __builtin_amdgcn_readfirstlane(a.prec);
+    u.radix = __builtin_amdgcn_readfirstlane(a.radix);
     return u;
 }
 
@@ -598,21 +606,21 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     // unrolled so that several global loads are in flight at once
     if (j.beta == 0.0) {
 #pragma unroll 4
-        for (int t = tid; t < N; t += WG) lds[t] = make_double2(t < j.n_in ? j.src[t] : 0.0, 0.0);
+        for (int t = tid; t < N; t += WG) lds[px(t)] = make_double2(t < j.n_in ? j.src[t] : 0.0, 0.0);
     } else {
         for (int t = tid; t < N; t += WG)
-            lds[t] = make_double2(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0);
+            lds[px(t)] = make_double2(t < j.n_in ? tilt_in(j.src[t], j.beta, t, j.tc) : 0.0, 0.0);
     }
     __syncthreads();
-    lds_dif(lds, lgN, 1, twl);
+    lds_dif(lds, lgN, 1, twl, j.radix);
     // P(-theta) = conj(P(theta)): evaluate f <= N/2 and apply to both mirrors.
     if (spec) {
 #pragma unroll 4
         for (int f = tid; f <= N / 2; f += WG) {
             const double2 m = spec[f];
             const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
-            lds[t1] = cmul(lds[t1], m);
-            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
+            lds[px(t1)] = cmul(lds[px(t1)], m);
+            if (t2 != t1) lds[px(t2)] = cmulc(lds[px(t2)], m);
         }
     } else {
         for (int f = tid; f <= N / 2; f += WG) {
@@ -620,13 +628,14 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
             bin_trig_lds(twl, f, lgN, cs, sn, sh);
             const double2 m = kernel_power(q, cs, sn, sh);
             const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
-            lds[t1] = cmul(lds[t1], m);
-            if (t2 != t1) lds[t2] = cmulc(lds[t2], m);
+            lds[px(t1)] = cmul(lds[px(t1)], m);
+            if (t2 != t1) lds[px(t2)] = cmulc(lds[px(t2)], m);
         }
     }
     __syncthreads();
-    lds_dit_inv(lds, lgN, 1, twl);
-    for (ll t = tid; t < j.n_out; t += WG) j.dst[t] = tilt_out(lds[j.out_off + t].x * invN, j.beta, j.out_off + t, j.tc);
+    lds_dit_inv(lds, lgN, 1, twl, j.radix);
+    for (ll t = tid; t < j.n_out; t += WG)
+        j.dst[t] = tilt_out(lds[px((int)(j.out_off + t))].x * invN, j.beta, j.out_off + t, j.tc);
     __syncthreads();
 }
 
@@ -643,20 +652,20 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), n1 = t >> lgC;
         const ll idx = (ll)n1 * N2 + n20 + c;
-        lds[c * N1 + n1] = make_double2(idx < j.n_in ? j.src[idx] : 0.0, 0.0);
+        lds[px(c * N1 + n1)] = make_double2(idx < j.n_in ? j.src[idx] : 0.0, 0.0);
     }
     if (j.beta != 0.0)  // the same elements, in the same threads: no barrier needed in between
         for (int t = tid; t < NLDS; t += WG) {
             const int c = t & (C - 1), n1 = t >> lgC;
-            lds[c * N1 + n1].x = tilt_in(lds[c * N1 + n1].x, j.beta, (ll)n1 * N2 + n20 + c, j.tc);
+            lds[px(c * N1 + n1)].x = tilt_in(lds[px(c * N1 + n1)].x, j.beta, (ll)n1 * N2 + n20 + c, j.tc);
         }
     __syncthreads();
-    lds_dif(lds, lg1, C, twl);
+    lds_dif(lds, lg1, C, twl, j.radix);
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
         const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
-        j.scr[(ll)p1 * N2 + n2] = cmul(lds[c * N1 + p1], w);
+        j.scr[(ll)p1 * N2 + n2] = cmul(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
 }
@@ -673,9 +682,9 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
     const ll k1 = bitrev(p1, lg1);
     double2 *row = j.scr + (ll)p1 * N2;
 #pragma unroll 4
-    for (int t = tid; t < N2; t += WG) lds[t] = row[t];
+    for (int t = tid; t < N2; t += WG) lds[px(t)] = row[t];
     __syncthreads();
-    lds_dif(lds, lg2, 1, twl);
+    lds_dif(lds, lg2, 1, twl, j.radix);
     if (spec) {
         // bin f = k1 + N1 k2; above N/2 the mirror's conjugate
         const ll N = ll(1) << lgN;
@@ -683,7 +692,7 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         for (int t = tid; t < N2; t += WG) {
             const ll f = k1 + (ll(bitrev(t, lg2)) << lg1);
             const double2 e = spec[f <= N / 2 ? f : N - f];
-            lds[t] = cmul(lds[t], f <= N / 2 ? e : make_double2(e.x, -e.y));
+            lds[px(t)] = cmul(lds[px(t)], f <= N / 2 ? e : make_double2(e.x, -e.y));
         }
     } else {
         double sr, cr;
@@ -694,12 +703,12 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         for (int t = tid; t < N2; t += WG) {
             double cs, sn, sh;
             bin_trig_rows(twl, r1, r2, (int)bitrev(t, lg2), cs, sn, sh);
-            lds[t] = cmul(lds[t], kernel_power(q, cs, sn, sh));
+            lds[px(t)] = cmul(lds[px(t)], kernel_power(q, cs, sn, sh));
         }
     }
     __syncthreads();
-    lds_dit_inv(lds, lg2, 1, twl);
-    for (int t = tid; t < N2; t += WG) row[t] = lds[t];
+    lds_dit_inv(lds, lg2, 1, twl, j.radix);
+    for (int t = tid; t < N2; t += WG) row[t] = lds[px(t)];
     __syncthreads();
 }
 
@@ -716,21 +725,21 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
 #pragma unroll 4
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), p1 = t >> lgC;
-        lds[c * N1 + p1] = j.scr[(ll)p1 * N2 + n20 + c];
+        lds[px(c * N1 + p1)] = j.scr[(ll)p1 * N2 + n20 + c];
     }
     for (int t = tid; t < NLDS; t += WG) {  // the same elements, in the same threads
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
         const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
-        lds[c * N1 + p1] = cmulc(lds[c * N1 + p1], w);
+        lds[px(c * N1 + p1)] = cmulc(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
-    lds_dit_inv(lds, lg1, C, twl);
+    lds_dit_inv(lds, lg1, C, twl, j.radix);
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), n1 = t >> lgC;
         const ll idx = (ll)n1 * N2 + n20 + c;
         if (idx >= j.out_off && idx < j.out_off + j.n_out)
-            j.dst[idx - j.out_off] = tilt_out(lds[c * N1 + n1].x * invN, j.beta, idx, j.tc);
+            j.dst[idx - j.out_off] = tilt_out(lds[px(c * N1 + n1)].x * invN, j.beta, idx, j.tc);
     }
     __syncthreads();
 }
@@ -1594,7 +1603,7 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
 {
     if (a.desc < 0 || a.desc >= n || a.kind < K_DIRECT || a.kind > K_4STEP || a.lgN < 1 || a.lgN > LG_TW ||
         ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN) ||
-        a.prec < 0 || a.prec > 1 || (a.kind != K_DIRECT && a.prec != prec))
+        a.prec < 0 || a.prec > 1 || (a.kind != K_DIRECT && a.prec != prec) || a.radix < 2 || a.radix > 3)
         return false;
     const Desc d = descs[a.desc];
     if (d.model < 0) return false;
@@ -1606,7 +1615,7 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
     if (a.kind == K_LDS && a.lgN > lds_lg(prec)) return false;  // must fit the LDS buffer
     if (a.kind == K_4STEP) {
         const char *c0 = (const char *)a.scr, *c1 = (const char *)(a.scr + (ll(1) << a.lgN));
-        if (c0 < lo || c1 > hi || a.lgN <= lds_lg(prec)) return false;
+        if (c0 < lo || c1 > hi || a.lgN <= LG_NLDS) return false;  // N1 >= 2 row tiles
     }
     return true;
 }
@@ -1815,8 +1824,11 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     if (lgN < 1) lgN = 1;
     a.lgN = lgN;
     const bool direct = beta == 0.0 && h <= cx.tn.direct_max_h && n_in <= cx.tn.direct_max_n;
-    a.kind = direct ? K_DIRECT : (lgN <= lds_lg(PREC) ? K_LDS : K_4STEP);
+    // FP64 transforms of up to 2^lds_lg64 points (11 or 12, tuned) run whole in LDS
+    a.kind = direct ? K_DIRECT : (lgN <= (PREC ? LG_NLDS : cx.tn.lds_lg64) ? K_LDS : K_4STEP);
     a.prec = direct ? 0 : PREC;  // direct stepping is always FP64
+    a.radix = cx.tn.radix;
+    a.pad = 0;
     a.nph = a.kind == K_4STEP ? 3 : 1;
     a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
     const ll need = a.kind == K_4STEP ? (ll(1) << lgN) : 0;
@@ -2944,8 +2956,9 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
 solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__restrict__ tw, double *price, ll *bnd,
              ll bnd_stride, int32_t *err, Stats *stats, Pool pl, Tune tn)
 {
-    __shared__ double2 lds[PREC ? NLDS : NLDS64];  // FFT tiles (mixed: NLDS split-FP32 values)
-    __shared__ double2 twl[NLDS + 1];  // e^{-2 pi i t / 4096}, t <= 2048
+    // FFT tiles (FP64: NLDS64 values at padded indices px; mixed: NLDS split-FP32 values)
+    __shared__ double2 lds[PREC ? NLDS : NLDS64 + NLDS64 / 8];
+    __shared__ double2 twl[NLDS + 1 + (NLDS + 1) / 8 + 1];  // e^{-2 pi i t / 4096} at px(t), t <= 2048
     __shared__ float4 twf[PREC ? NLDS / 2 : 1];  // split twiddles (mixed precision only)
     __shared__ Frame stk[MAXD];
     __shared__ int sp_sh, err_sh;
@@ -2955,7 +2968,7 @@ solve_kernel(const Desc *__restrict__ descs, ll n, char *ws, const double2 *__re
     __shared__ Shared sh;
 
     const int tid = threadIdx.x;
-    for (int t = tid; t <= NLDS; t += WG) twl[t] = tw[(ll)t << (LG_TW - LG_NLDS - 1)];
+    for (int t = tid; t <= NLDS; t += WG) twl[px(t)] = tw[(ll)t << (LG_TW - LG_NLDS - 1)];
     if (PREC) {
         for (int t = tid; t < NLDS / 2; t += WG) {
             const double2 w = tw[(ll)t << (LG_TW - LG_NLDS)];  // e^{-2 pi i t / 2048}

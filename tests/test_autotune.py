@@ -26,14 +26,17 @@ def test_server_table_lists_every_class():
 
 
 def test_candidates_cover_the_tuned_fields():
-    keys = set(autotune.CANDIDATES[0])
-    assert all(set(c) == keys for c in autotune.CANDIDATES)
+    keys = set(autotune.SCHEDULE_KEYS)
+    assert all(set(dict(autotune.SCHEDULE_DEFAULTS, **c)) == keys for c in autotune.CANDIDATES)
     assert keys <= {"workgroups", "pub_min_lg", "pub_direct", "direct_max_h", "direct_max_n", "helper_idle_us",
-                    "timeout_ms"}
+                    "timeout_ms", "lds_max_lg", "radix_lg"}
+    # FFT schedules are among the candidates: LDS transform size and pass radix
+    assert {dict(autotune.SCHEDULE_DEFAULTS, **c)["lds_max_lg"] for c in autotune.CANDIDATES} == {11, 12}
+    assert {dict(autotune.SCHEDULE_DEFAULTS, **c)["radix_lg"] for c in autotune.CANDIDATES} == {2, 3}
 
 
 def test_committed_table_is_well_formed():
     t = autotune.load_cache()
     for key, rec in t.get("classes", {}).items():
         assert key == autotune.class_key(rec["model"], rec["lg"], rec["precision"])
-        assert set(rec["best"]) == set(autotune.CANDIDATES[0])
+        assert set(rec["best"]) <= set(autotune.SCHEDULE_KEYS)

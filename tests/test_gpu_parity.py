@@ -204,6 +204,8 @@ SCHEDULES = [
     ("wide direct", dict(direct_max_h=320, direct_max_n=2048)),
     ("no direct", dict(direct_max_h=0)),
     ("publish all", dict(pub_min_lg=1, pub_direct=1, direct_max_h=320, direct_max_n=2048)),
+    ("2048-point LDS transforms", dict(lds_max_lg=11, pub_min_lg=12)),
+    ("radix-4 passes", dict(radix_lg=2, lds_max_lg=11, pub_min_lg=11)),
 ]
 
 
