@@ -1109,8 +1109,11 @@ __device__ __forceinline__ int resolve_block(unsigned mlo, unsigned mhi, int nb,
 // e <- u e + K(u-1); f1 (f2) is the exercise value of column c0+64 (c0+65) in
 // the row being read, the cells beyond the band that enter through the
 // shift's fill.  Returns whether the lane's new cell is red (continuation >=
-// exercise, continuation finite).
-template <bool TRI>
+// exercise, continuation finite).  GUARD = false is the fast form used by the
+// count-based block check: the max of continuation and exercise value, which
+// differs from the guarded rule only once a value has overflowed -- the block
+// then ends with a non-finite cell and is walked again with GUARD = true.
+template <bool TRI, bool GUARD>
 __device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, double &f2, double u, double ku, double w0,
                                          double w1, double w2)
 {
@@ -1127,6 +1130,10 @@ __device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, doubl
         c = fma(w1, g1, w0 * g);
     }
     e = fma(e, u, ku);
+    if (!GUARD) {
+        g = vmax_f64(c, e);
+        return c >= e;
+    }
     // Definition 2.1 with the non-finite guard: c >= e and c finite (then e
     // is finite too).  A continuation value that overflowed marks an exercise
     // cell, whose value is its exercise value.
@@ -1186,13 +1193,13 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
             if (nb == 64) {
 #pragma unroll
                 for (int r = 0; r < 64; ++r) {
-                    const bool red = lat_step<TRI>(gg, e, f1, f2, u, ku, w0, w1, w2);
+                    const bool red = lat_step<TRI, false>(gg, e, f1, f2, u, ku, w0, w1, w2);
                     cnt += red ? 1 : 0;
                     lastr = red ? r : lastr;
                 }
             } else {
                 for (int r = 0; r < nb; ++r) {
-                    const bool red = lat_step<TRI>(gg, e, f1, f2, u, ku, w0, w1, w2);
+                    const bool red = lat_step<TRI, false>(gg, e, f1, f2, u, ku, w0, w1, w2);
                     cnt += red ? 1 : 0;
                     lastr = red ? r : lastr;
                 }
@@ -1201,7 +1208,9 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
             const bool prefix = (cnt == 0) || (lastr == cnt - 1);
             const bool shape = (l > L0) ? (cnt == 0)
                                         : (l == L0 || cnt > nxt || (cnt == nb && nxt == nb));
-            if (__ballot(!(prefix && shape)) == 0ull) {
+            // a non-finite value (overflow) anywhere: the guarded walk below decides
+            const bool finite = (gg < INFINITY) && (e < INFINITY);
+            if (__ballot(!(prefix && shape && finite)) == 0ull) {
                 g = gg;
                 bc = c0 - 1 + (int)__popcll(__ballot(cnt == nb));
                 if (bnd) {
@@ -1216,7 +1225,7 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
             double e = e0, f1 = f10, f2 = f20;
             unsigned mlo = 0, mhi = 0;
             for (int r = 0; r < nb; ++r) {
-                const bool red = lat_step<TRI>(g, e, f1, f2, u, ku, w0, w1, w2);
+                const bool red = lat_step<TRI, true>(g, e, f1, f2, u, ku, w0, w1, w2);
                 // lanes beyond the row's last column are outside the lattice
                 const unsigned long long m = __ballot(red) & row_mask(wr * (itop - 1 - r) - c0);
                 mlo = writelane(mlo, (unsigned)m, r);
