@@ -3,15 +3,19 @@
 The tunables are those of ``aop_tuning``: which correlations are handed to
 the work pool (``pub_min_lg``: the smallest published transform, 2^lg points),
 which short correlations are stepped directly instead of transformed
-(``direct_max_h``, ``direct_max_n``) and the persistent grid size.  The pool
-settings change no result (each option's arithmetic is the same whoever
-computes a tile); the direct-stepping thresholds choose between two exact
-evaluations of the same linear map, so they move prices by rounding only.  A
-candidate is accepted if its prices agree with the first candidate's within
-1e-9 (relative, or 1e-13 K below 1e-3 K, the FP64 parity bar).
+(``direct_max_h``, ``direct_max_n``), the largest FP64 transform held whole in
+LDS (``lds_max_lg``), the radix of the LDS butterfly passes (``radix_lg``) and
+the persistent grid size.  The pool settings change no result (each option's
+arithmetic is the same whoever computes a tile); the other knobs choose
+between exact evaluations of the same linear map, so they move prices by
+rounding only.  A candidate is accepted if its prices agree with the first
+candidate's within 1e-9 (relative, or 1e-13 K below 1e-3 K, the FP64 parity
+bar).
 
 For each size class (model, ceil(log2 T), precision) the tuner times every
-candidate schedule on a seeded batch of that class and keeps the fastest; the
+candidate schedule on a seeded batch of that class (median of four launches)
+and keeps the fastest, unless it beats the first (library default) schedule by
+no more than ``NOISE``; the
 table is stored as JSON per device architecture and applied per class:
 ``apply(ctx, model, T, precision)`` sets a context's tuning before a batch
 launch, and ``server_table`` gives the per-class table a server takes.
