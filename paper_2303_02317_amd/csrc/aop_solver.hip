@@ -35,7 +35,8 @@ namespace aop {
 #define NLDS64 4096  // FP64 transforms of up to this many points run whole in LDS (64 KB)
 #define LG_NLDS64 12
 #define MAXD 48    // recursion depth bound (log2 of 2^22 plus slack)
-#define BAND 64    // cells held by the band walker (one per lane)
+#define BAND 64    // cells held by the BSM and Bermudan band walkers (one per lane)
+#define BAND_LAT 128  // cells held by the lattice band walker (two per lane)
 
 typedef long long ll;
 
@@ -60,6 +61,13 @@ __device__ __forceinline__ Mp make_mp(const Desc &d)
     p.w1 = d.w1;
     p.w2 = d.w2;
     return p;
+}
+
+// Cells of a band leaf: the lattice walker holds two per lane, the BSM and
+// Bermudan walkers one.
+__device__ __forceinline__ ll band_width(const Mp &p)
+{
+    return (p.model != BSM && p.ex_every <= 1) ? BAND_LAT : BAND;
 }
 
 // Wave-uniform copy of a value that is uniform by construction.
@@ -1104,61 +1112,72 @@ __device__ __forceinline__ int resolve_block(unsigned mlo, unsigned mhi, int nb,
     return bc;
 }
 
-// One row step of a lattice band (TRI: trinomial).  Lane l holds column c0+l;
-// e is the lane's exercise value S u^{.} - K, advanced to the new row by
-// e <- u e + K(u-1); f1 (f2) is the exercise value of column c0+64 (c0+65) in
-// the row being read, the cells beyond the band that enter through the
-// shift's fill.  Returns whether the lane's new cell is red (continuation >=
-// exercise, continuation finite).  GUARD = false is the fast form used by the
-// count-based block check: the max of continuation and exercise value, which
-// differs from the guarded rule only once a value has overflowed -- the block
-// then ends with a non-finite cell and is walked again with GUARD = true.
+// One row step of a lattice band (TRI: trinomial).  Lane l holds columns
+// c0+2l (A) and c0+2l+1 (B); eA, eB are their exercise values S u^{.} - K,
+// advanced to the new row by e <- u e + K(u-1); f1 (f2) is the exercise value
+// of column c0+128 (c0+129) in the row being read, the cells beyond the band
+// that enter through the shift's fill.  rA, rB: whether the lane's new cells
+// are red (continuation >= exercise, continuation finite).  GUARD = false is
+// the fast form used by the count-based block check: the max of continuation
+// and exercise value, which differs from the guarded rule only once a value
+// has overflowed -- the block then ends with a non-finite cell and is walked
+// again with GUARD = true.
 template <bool TRI, bool GUARD>
-__device__ __forceinline__ bool lat_step(double &g, double &e, double &f1, double &f2, double u, double ku, double w0,
-                                         double w1, double w2)
+__device__ __forceinline__ void lat_step(double &gA, double &gB, double &eA, double &eB, double &f1, double &f2,
+                                         double u, double ku, double w0, double w1, double w2, bool &rA, bool &rB)
 {
-    // only lane 63 reads the fills, and there the shifted value is the fill
-    // itself: the next fill is computed from the shifted register
-    const double g1 = dpp_dn1(g, f1);
-    f1 = fma(g1, u, ku);
-    double c;
+    // column c0+2l+2 (and c0+2l+3) is the next lane's A (B) cell; lane 63
+    // receives the fills, and the next fills are computed from its shifted
+    // registers
+    const double nA = dpp_dn1(gA, f1);
+    f1 = fma(nA, u, ku);
+    double cA, cB;
     if (TRI) {
-        const double g2 = dpp_dn1(g1, f2);
-        f2 = fma(g2, u, ku);
-        c = fma(w2, g2, fma(w1, g1, w0 * g));
+        const double nB = dpp_dn1(gB, f2);
+        f2 = fma(nB, u, ku);
+        cA = fma(w2, nA, fma(w1, gB, w0 * gA));
+        cB = fma(w2, nB, fma(w1, nA, w0 * gB));
     } else {
-        c = fma(w1, g1, w0 * g);
+        cA = fma(w1, gB, w0 * gA);
+        cB = fma(w1, nA, w0 * gB);
     }
-    e = fma(e, u, ku);
+    eA = fma(eA, u, ku);
+    eB = fma(eB, u, ku);
     if (!GUARD) {
-        g = vmax_f64(c, e);
-        return c >= e;
+        gA = vmax_f64(cA, eA);
+        gB = vmax_f64(cB, eB);
+        rA = cA >= eA;
+        rB = cB >= eB;
+        return;
     }
     // Definition 2.1 with the non-finite guard: c >= e and c finite (then e
     // is finite too).  A continuation value that overflowed marks an exercise
     // cell, whose value is its exercise value.
-    const bool red = (c >= e) && (c < INFINITY);
-    g = red ? c : e;
-    return red;
+    rA = (cA >= eA) && (cA < INFINITY);
+    rB = (cB >= eB) && (cB < INFINITY);
+    gA = rA ? cA : eA;
+    gB = rB ? cB : eB;
 }
 
 // Rows i0-1 .. i0-h of a lattice (binomial: row i has columns 0..i, cell j
 // reads j and j+1; trinomial: columns 0..2i, cell j reads j, j+1, j+2) from
-// row i0, whose red cells are [c0, b] (b - c0 + 1 <= BAND); columns >= c0
-// only.  Writes the red cells of row i0-h to dst, the boundary of each row to
-// bnd (may be NULL); returns the last red column of row i0-h.  *v0 receives
-// the final value of column c0.
+// row i0, whose red cells are [c0, b] (b - c0 + 1 <= BAND_LAT); columns >= c0
+// only, two per lane.  Writes the red cells of row i0-h to dst, the boundary
+// of each row to bnd (may be NULL); returns the last red column of row i0-h.
+// *v0 receives the final value of column c0.
 //
-// Rows go in blocks of up to 64.  The fast form of a block keeps, per lane,
+// Rows go in blocks of up to 64.  The fast form of a block keeps, per cell,
 // only the number of red rows and the last red row; the block is accepted if
-// these show the structure of Corollary 2.6 / Theorem 4.2 -- each lane red in
+// these show the structure of Corollary 2.6 / Theorem 4.2 -- each cell red in
 // a prefix of the rows, the red cells of every row contiguous from c0, and the
 // boundary dropping by at most one cell per row -- and every row of the block
-// lies inside the lattice for all 64 lanes.  Then row r's boundary is c0 - 1
-// plus the number of lanes red for more than r rows.  Otherwise (a near-tie
+// lies inside the lattice for all 128 cells.  Then row r's boundary is c0 - 1
+// plus the number of cells red for more than r rows.  Otherwise (a near-tie
 // cell, rows near the apex) the block is stepped again from its saved first
-// row with the same arithmetic, collecting each row's ballot, and resolved
-// with the previous-cell rule.
+// row with the same arithmetic and each row's boundary follows from the
+// previous one by the one-cell rule (the previous boundary cell red: it stays;
+// green: it moves left by one), or, below an entirely red trinomial row, as
+// the row's last red cell.
 template <bool TRI>
 __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const double *src, double *dst,
                                        ll *bnd, double *v0)
@@ -1166,13 +1185,14 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
     // indices fit in 32 bits (T <= 2^21): scalar 32-bit bookkeeping
     const int i0 = (int)uni(i0_), c0 = (int)uni(c0_), h = (int)uni(h_), b = (int)uni(b_);
     const int l = threadIdx.x & 63;
-    const int j = c0 + l;
+    const int jA = c0 + 2 * l, jB = jA + 1;
     const int cs = TRI ? 1 : 2;   // exercise exponent: S u^{cs j - i}
     const int wr = TRI ? 2 : 1;   // last column of row i: wr i
     const double S = p.S, K = p.K, a = p.a, w0 = p.w0, w1 = p.w1, w2 = TRI ? p.w2 : 0.0;
     const double u = exp(a);
     const double ku = K * (u - 1.0);
-    double g = (j <= b) ? src[j] : ((j <= wr * i0) ? S * exp((double)(cs * j - i0) * a) - K : 0.0);
+    double gA = (jA <= b) ? src[jA] : ((jA <= wr * i0) ? S * exp((double)(cs * jA - i0) * a) - K : 0.0);
+    double gB = (jB <= b) ? src[jB] : ((jB <= wr * i0) ? S * exp((double)(cs * jB - i0) * a) - K : 0.0);
     int bc = b;
     // The carried exercise values e <- u e + K(u-1) amplify their rounding by
     // u per row: blocks (and re-seeding with exp) are cut to at most 4/a rows,
@@ -1182,62 +1202,90 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
     for (int k0 = 0; k0 < h; k0 += blk) {
         const int nb = (h - k0) < blk ? (h - k0) : blk;
         const int itop = i0 - k0;  // row above the block
-        const double e0 = S * exp((double)(cs * j - itop) * a) - K;
-        const double f10 = S * exp((double)(cs * (c0 + BAND) - itop) * a) - K;
+        const double eA0 = S * exp((double)(cs * jA - itop) * a) - K;
+        const double eB0 = S * exp((double)(cs * jB - itop) * a) - K;
+        const double f10 = S * exp((double)(cs * (c0 + BAND_LAT) - itop) * a) - K;
         const double f20 = TRI ? fma(f10, u, ku) : 0.0;
         const int L0 = bc - c0;
         bool done = false;
-        if (wr * (itop - nb) - c0 >= 63 && L0 >= 0 && L0 <= 63) {
-            double gg = g, e = e0, f1 = f10, f2 = f20;
-            int cnt = 0, lastr = -1;
+        if (wr * (itop - nb) - c0 >= BAND_LAT - 1 && L0 >= 0 && L0 <= BAND_LAT - 1) {
+            double ga = gA, gb = gB, ea = eA0, eb = eB0, f1 = f10, f2 = f20;
+            int na = 0, nbb = 0, la = -1, lb = -1;
+            bool rA, rB;
             if (nb == 64) {
 #pragma unroll
                 for (int r = 0; r < 64; ++r) {
-                    const bool red = lat_step<TRI, false>(gg, e, f1, f2, u, ku, w0, w1, w2);
-                    cnt += red ? 1 : 0;
-                    lastr = red ? r : lastr;
+                    lat_step<TRI, false>(ga, gb, ea, eb, f1, f2, u, ku, w0, w1, w2, rA, rB);
+                    na += rA ? 1 : 0;
+                    la = rA ? r : la;
+                    nbb += rB ? 1 : 0;
+                    lb = rB ? r : lb;
                 }
             } else {
                 for (int r = 0; r < nb; ++r) {
-                    const bool red = lat_step<TRI, false>(gg, e, f1, f2, u, ku, w0, w1, w2);
-                    cnt += red ? 1 : 0;
-                    lastr = red ? r : lastr;
+                    lat_step<TRI, false>(ga, gb, ea, eb, f1, f2, u, ku, w0, w1, w2, rA, rB);
+                    na += rA ? 1 : 0;
+                    la = rA ? r : la;
+                    nbb += rB ? 1 : 0;
+                    lb = rB ? r : lb;
                 }
             }
-            const int nxt = __shfl_down(cnt, 1, 64);
-            const bool prefix = (cnt == 0) || (lastr == cnt - 1);
-            const bool shape = (l > L0) ? (cnt == 0)
-                                        : (l == L0 || cnt > nxt || (cnt == nb && nxt == nb));
+            // counts of the next cells: cell 2l+1 is this lane's B, cell 2l+2
+            // the next lane's A (cell 127 never needs one: it is at or beyond L0)
+            const int nxtA = nbb;
+            const int nxtB = __shfl_down(na, 1, 64);
+            const int xA = 2 * l, xB = 2 * l + 1;
+            const bool okA = ((na == 0) || (la == na - 1)) &&
+                             ((xA > L0) ? (na == 0) : (xA == L0 || na > nxtA || (na == nb && nxtA == nb)));
+            const bool okB = ((nbb == 0) || (lb == nbb - 1)) &&
+                             ((xB > L0) ? (nbb == 0) : (xB == L0 || nbb > nxtB || (nbb == nb && nxtB == nb)));
             // a non-finite value (overflow) anywhere: the guarded walk below decides
-            const bool finite = (gg < INFINITY) && (e < INFINITY);
-            if (__ballot(!(prefix && shape && finite)) == 0ull) {
-                g = gg;
-                bc = c0 - 1 + (int)__popcll(__ballot(cnt == nb));
+            const bool finite = (ga < INFINITY) && (ea < INFINITY) && (gb < INFINITY) && (eb < INFINITY);
+            if (__ballot(!(okA && okB && finite)) == 0ull) {
+                gA = ga;
+                gB = gb;
+                bc = c0 - 1 + (int)__popcll(__ballot(na == nb)) + (int)__popcll(__ballot(nbb == nb));
                 if (bnd) {
+                    // lane r: row r's boundary, c0 - 1 plus the cells red for more than r rows
                     int q = c0 - 1;
-                    for (int m = 0; m <= L0; ++m) q += (__builtin_amdgcn_readlane(cnt, m) > l) ? 1 : 0;
+                    for (int m = 0; 2 * m <= L0; ++m) {
+                        q += (__builtin_amdgcn_readlane(na, m) > l) ? 1 : 0;
+                        q += (__builtin_amdgcn_readlane(nbb, m) > l) ? 1 : 0;
+                    }
                     if (l < nb) bnd[itop - 1 - l] = q;
                 }
                 done = true;
             }
         }
         if (!done) {
-            double e = e0, f1 = f10, f2 = f20;
-            unsigned mlo = 0, mhi = 0;
+            double ea = eA0, eb = eB0, f1 = f10, f2 = f20;
+            int q = 0;
             for (int r = 0; r < nb; ++r) {
-                const bool red = lat_step<TRI, true>(g, e, f1, f2, u, ku, w0, w1, w2);
-                // lanes beyond the row's last column are outside the lattice
-                const unsigned long long m = __ballot(red) & row_mask(wr * (itop - 1 - r) - c0);
-                mlo = writelane(mlo, (unsigned)m, r);
-                mhi = writelane(mhi, (unsigned)(m >> 32), r);
+                bool rA, rB;
+                lat_step<TRI, true>(gA, gB, ea, eb, f1, f2, u, ku, w0, w1, w2, rA, rB);
+                // cells beyond the row's last column are outside the lattice
+                const int i = itop - 1 - r;
+                const int lim = wr * i - c0;
+                const unsigned long long mA = __ballot(rA) & row_mask(lim < 0 ? -1 : lim >> 1);
+                const unsigned long long mB = __ballot(rB) & row_mask(lim < 1 ? -1 : (lim - 1) >> 1);
+                if (TRI && bc >= wr * (i + 1)) {
+                    // the row above was entirely red: this row's last red cell
+                    int x = -1;
+                    if (mB) x = 2 * (63 - (int)__clzll(mB)) + 1;
+                    if (mA) x = max(x, 2 * (63 - (int)__clzll(mA)));
+                    bc = c0 + x;
+                } else {
+                    const int lc = bc - c0;
+                    if (lc >= 0 && lc < BAND_LAT) bc -= ((((lc & 1) ? mB : mA) >> (lc >> 1)) & 1ull) ? 0 : 1;
+                }
+                q = (l == r) ? bc : q;
             }
-            int q;
-            bc = resolve_block<TRI>(mlo, mhi, nb, bc, c0, 0, -1, &q, 2 * itop);
             if (bnd && l < nb) bnd[itop - 1 - l] = q;
         }
     }
-    if (j <= bc) dst[j] = g;
-    if (v0 && l == 0) *v0 = g;
+    if (jA <= bc) dst[jA] = gA;
+    if (jB <= bc) dst[jB] = gB;
+    if (v0 && l == 0) *v0 = gA;
     return bc;
 }
 
@@ -2165,6 +2213,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     const ll kstep = (d.model == BINOMIAL && d.ex_every > 1) ? d.ex_every : 1;
     const ll span = (d.model == BINOMIAL) ? kstep : 2;
     const ll timeout = cx.tn.timeout_ticks;
+    const ll bw = band_width(d);
     if (cap > WQ) cap = WQ;  // one outstanding correlation per frame fits the queue
     // The frame being worked on (depth sp) lives in registers; the stack
     // holds its ancestors, each stored when its child was entered.
@@ -2188,10 +2237,10 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     };
     // leaf test and its range checks (lattice: red cells [c0, b]; BSM: centred on c0)
     auto is_leaf = [&](const Frame &f) -> bool {
-        return (d.model != BSM) ? (f.b - f.c0 + 1 <= BAND) : (f.h <= (BAND - 2) / 2);
+        return (d.model != BSM) ? (f.b - f.c0 + 1 <= bw) : (f.h <= (BAND - 2) / 2);
     };
     auto leaf_ok = [&](const Frame &f) -> bool {
-        return (d.model != BSM) ? (in_ws(cx, f.src, f.c0, f.b) && in_ws(cx, f.dst, f.c0, f.c0 + BAND - 1))
+        return (d.model != BSM) ? (in_ws(cx, f.src, f.c0, f.b) && in_ws(cx, f.dst, f.c0, f.c0 + bw - 1))
                                 : (in_ws(cx, f.src, f.c0 + 1, f.c0 + 2 * f.h) && in_ws(cx, f.dst, f.c0 - f.h, f.c0 + f.h));
     };
     Frame fr = uni_frame(root);
@@ -2215,7 +2264,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             const ll h1 = h / 2, h2 = h - h1;
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
-                if (nred <= BAND) {  // only a root can be a leaf: children that are leaves are walked inline
+                if (nred <= bw) {  // only a root can be a leaf: children that are leaves are walked inline
                     if (!leaf_ok(fr)) e = DEV_RANGE;
                     else leaf = true;
                     pop = true;
@@ -2418,7 +2467,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll h1 = h / 2, h2 = h - h1;
             const ll nred = b - c0 + 1;
             if (fr.stage == 0) {
-                if (nred <= BAND || (kstep <= BAND && wave_sized(d, cx.tn, nred, kstep * h))) {
+                if (nred <= band_width(d) || (kstep <= BAND && wave_sized(d, cx.tn, nred, kstep * h))) {
                     leaf = true;  // wave 0 solves it alone (band, or direct steps and bands)
                     pop = true;
                 } else if (kstep > 1 && h == 1) {
@@ -2742,7 +2791,7 @@ __device__ __forceinline__ double drive_lattice(const Ctx &cx, double *rowA, dou
             return d.S * exp((double)r0 * log(d.w1 * u + d.w0 / u)) - d.K * exp((double)r0 * log(d.w0 + d.w1));
         }
         const ll nred = b + 1;
-        if (nred <= BAND) {  // the band walks the leftover triangle to the root
+        if (nred <= band_width(d)) {  // the band walks the leftover triangle to the root
             const ll tb = clk();
             if (tid < 64) {
                 if (bin) band_bin(d, i0, 0, i0, b, src, dst, cx.bnd, val_sh);

@@ -13,7 +13,8 @@ import math
 
 import numpy as np
 
-BAND = 64
+BAND = 64        # BSM band walker: one cell per lane
+BAND_LAT = 128   # lattice band walker: two cells per lane
 BINOMIAL, TRINOMIAL, BSM = 0, 1, 2
 NONE = np.iinfo(np.int64).min
 
@@ -154,18 +155,18 @@ class Model:
         d, tri = self.d, self.d["model"] == TRINOMIAL
         ex = ex_tri if tri else ex_bin
         wmax = (lambda i: 2 * i) if tri else (lambda i: i)
-        if b - c0 + 1 > BAND:
+        if b - c0 + 1 > BAND_LAT:
             raise Geometry("band too narrow")
-        j = c0 + np.arange(BAND)
+        j = c0 + np.arange(BAND_LAT)
         g = np.where(j <= wmax(i0), ex(d, i0, j), 0.0)
         if b >= c0:
             g[:b - c0 + 1] = src.get(c0, b)
         bc = b
         for k in range(1, h + 1):
             i = i0 - k
-            gn1 = np.append(g[1:], ex(d, i + 1, c0 + BAND))
+            gn1 = np.append(g[1:], ex(d, i + 1, c0 + BAND_LAT))
             if tri:
-                gn2 = np.append(g[2:], [ex(d, i + 1, c0 + BAND), ex(d, i + 1, c0 + BAND + 1)])
+                gn2 = np.append(g[2:], [ex(d, i + 1, c0 + BAND_LAT), ex(d, i + 1, c0 + BAND_LAT + 1)])
                 c = d["w"][0] * g + d["w"][1] * gn1 + d["w"][2] * gn2
             else:
                 c = d["w"][0] * g + d["w"][1] * gn1
@@ -219,7 +220,7 @@ class Model:
         self.max_depth = max(self.max_depth, depth)
         span = 2 if self.d["model"] == TRINOMIAL else 1
         nred = b - c0 + 1
-        if nred <= BAND:
+        if nred <= BAND_LAT:
             return self.band_lat(i0, c0, h, b, src, dst)[0]
         h1, h2 = h // 2, h - h // 2
         mid = Buf(c0, b, "mid")
@@ -289,7 +290,7 @@ class Model:
                 self.bnd[:i0] = -1
                 return d["S"] - d["K"]
             nred = b + 1
-            if nred <= BAND:
+            if nred <= BAND_LAT:
                 _, v0 = self.band_lat(i0, 0, i0, b, src, dst)
                 return v0
             h = nred if not tri else nred // 2
