@@ -697,8 +697,9 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         // bin f = k1 + N1 k2; above N/2 the mirror's conjugate
         const ll N = ll(1) << lgN;
 #pragma unroll 4
-        for (int t = tid; t < N2; t += WG) {
-            const ll f = k1 + (ll(bitrev(t, lg2)) << lg1);
+        for (int k2 = tid; k2 < N2; k2 += WG) {
+            const int t = (int)bitrev(k2, lg2);
+            const ll f = k1 + ((ll)k2 << lg1);
             const double2 e = spec[f <= N / 2 ? f : N - f];
             lds[px(t)] = cmul(lds[px(t)], f <= N / 2 ? e : make_double2(e.x, -e.y));
         }
@@ -708,9 +709,14 @@ __device__ __forceinline__ void tile_rows(const Mp &p, const JobArgs &j, int til
         const double2 r1 = make_double2(cr, -sr);
         sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
         const double2 r2 = make_double2(cr, -sr);
-        for (int t = tid; t < N2; t += WG) {
+        // bins in natural order, so that the lanes of a wave hold neighbouring
+        // frequencies: the significant bins (|P|^h above e^-60, a narrow band
+        // around theta = 0 for long kernels) then fall in a few waves, and the
+        // others skip the transcendental part together
+        for (int k2 = tid; k2 < N2; k2 += WG) {
+            const int t = (int)bitrev(k2, lg2);
             double cs, sn, sh;
-            bin_trig_rows(twl, r1, r2, (int)bitrev(t, lg2), cs, sn, sh);
+            bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
             lds[px(t)] = cmul(lds[px(t)], kernel_power(q, cs, sn, sh));
         }
     }
@@ -839,8 +845,8 @@ __device__ __forceinline__ void tile_rows_ff(const Mp &p, const JobArgs &j, int 
     const double2 r1 = make_double2(cr, -sr);
     sincospi((double)k1 / (double)(ll(1) << lgN), &sr, &cr);
     const double2 r2 = make_double2(cr, -sr);
-    for (int t = tid; t < N2; t += WG) {
-        const int k2 = (int)bitrev(t, lg2);
+    for (int k2 = tid; k2 < N2; k2 += WG) {  // natural bin order, as in tile_rows
+        const int t = (int)bitrev(k2, lg2);
         double cs, sn, sh;
         bin_trig_rows(twl, r1, r2, k2, cs, sn, sh);
         st_cf(lds + t, cf_scale64(ld_cf(lds + t), kernel_power(q, cs, sn, sh)));
