@@ -480,17 +480,22 @@ __device__ __forceinline__ double2 twl_at(const double2 *twl, int t)  // any t i
 __device__ __forceinline__ int lds_lg(int prec) { return prec ? LG_NLDS : LG_NLDS64; }
 
 // Bin f of a transform of 2^lgN <= 4096 points: theta = 2 pi f / N, f <= N / 2.
-__device__ __forceinline__ void bin_trig_lds(const double2 *twl, ll f, int lgN, double &cs, double &sn, double &sh)
+__device__ __forceinline__ void bin_trig_lds(const double2 *twl, const double2 *__restrict__ tw, ll f, int lgN,
+                                             double &cs, double &sn, double &sh)
 {
     const double2 e = twl[px((int)(f << (12 - lgN)))];
     cs = e.x;
     sn = -e.y;
-    if (lgN <= LG_NLDS) {
-        sh = twl[px((int)(f << (11 - lgN)))].y;
-    } else {  // 4096 points: theta / 2 is not on the table's grid
-        double c2;
-        sincospi((double)f / (double)(ll(1) << lgN), &sh, &c2);
-    }
+    if (lgN <= LG_NLDS) sh = twl[px((int)(f << (11 - lgN)))].y;
+    else sh = tw[f << (LG_TW - lgN - 1)].y;  // 4096 points: theta / 2 from the 2^22 table
+}
+// The same for transforms of up to 2048 points (the LDS table alone).
+__device__ __forceinline__ void bin_trig_lds11(const double2 *twl, ll f, int lgN, double &cs, double &sn, double &sh)
+{
+    const double2 e = twl[px((int)(f << (12 - lgN)))];
+    cs = e.x;
+    sn = -e.y;
+    sh = twl[px((int)(f << (11 - lgN)))].y;
 }
 // Bin k1 + N1 k2 of a four-step transform (N = N1 * 2048): r1 = e^{-2 pi i k1/N}
 // and r2 = e^{-i pi k1/N} are the tile's row factors, the rest comes from LDS.
@@ -509,6 +514,17 @@ __device__ __forceinline__ double2 twiddle_n(ll m, int lgN)
     double sv, cv;
     sincospi((double)(2 * m) / (double)(ll(1) << lgN), &sv, &cv);
     return make_double2(cv, -sv);
+}
+// The same from the tables: m = m_hi 2^s + m_lo (N = 4096 * 2^s) gives
+// e^{-2 pi i m_hi / 4096} (LDS table) times e^{-2 pi i m_lo / N} (a stretch of
+// 2^s entries of the 2^22-point global table, which stays in cache).
+__device__ __forceinline__ double2 twiddle_tab(ll m, int lgN, const double2 *__restrict__ tw, const double2 *twl)
+{
+    if (lgN <= LG_NLDS + 1) return twl_at(twl, (int)(m << (LG_NLDS + 1 - lgN)));
+    const int s = lgN - (LG_NLDS + 1);
+    const double2 hi = twl_at(twl, (int)(m >> s));
+    const double2 lo = tw[(m & ((ll(1) << s) - 1)) << (LG_TW - lgN)];
+    return cmul(hi, lo);
 }
 
 // cs, sn: cos and sin of theta; sh: +-sin(theta/2) (only its square is used).
@@ -633,7 +649,7 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     } else {
         for (int f = tid; f <= N / 2; f += WG) {
             double cs, sn, sh;
-            bin_trig_lds(twl, f, lgN, cs, sn, sh);
+            bin_trig_lds(twl, tw, f, lgN, cs, sn, sh);
             const double2 m = kernel_power(q, cs, sn, sh);
             const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
             lds[px(t1)] = cmul(lds[px(t1)], m);
@@ -672,7 +688,7 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
+        const double2 w = twiddle_tab((n2 * k1) & (N - 1), lgN, tw, twl);
         j.scr[(ll)p1 * N2 + n2] = cmul(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
@@ -744,7 +760,7 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
     for (int t = tid; t < NLDS; t += WG) {  // the same elements, in the same threads
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = twiddle_n((n2 * k1) & (N - 1), lgN);
+        const double2 w = twiddle_tab((n2 * k1) & (N - 1), lgN, tw, twl);
         lds[px(c * N1 + p1)] = cmulc(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
@@ -787,7 +803,7 @@ __device__ __forceinline__ void tile_lds_ff(const Mp &p, const JobArgs &j, float
     lds_dif_ff(lds, lgN, 1, twf);
     for (ll f = tid; f <= N / 2; f += WG) {
         double cs, sn, sh;
-        bin_trig_lds(twl, f, lgN, cs, sn, sh);
+        bin_trig_lds11(twl, f, lgN, cs, sn, sh);  // N <= 2048
         const double2 m = kernel_power(q, cs, sn, sh);
         const unsigned t1 = bitrev((unsigned)f, lgN), t2 = bitrev((unsigned)((N - f) & (N - 1)), lgN);
         st_cf(lds + t1, cf_scale64(ld_cf(lds + t1), m));
@@ -995,13 +1011,14 @@ __device__ __forceinline__ ll clk() { return (ll)__builtin_amdgcn_s_memtime(); }
 // points, bins f = 0 .. N/2 (the rest is its mirror's conjugate), into out.
 // Sub-trapezoids of one level share their heights, so a driver reuses these
 // arrays across its private correlations (the spectrum cache in Ctx).
-__device__ __forceinline__ void spec_fill(const Mp &p, ll h, int lgN, double2 *out, const double2 *twl)
+__device__ __forceinline__ void spec_fill(const Mp &p, ll h, int lgN, double2 *out, const double2 *twl,
+                                          const double2 *__restrict__ tw)
 {
     const Spec q = make_spec(p, h, 0.0, 0.0);
     const ll N = ll(1) << lgN;
     for (ll f = threadIdx.x; f <= N / 2; f += WG) {
         double cs, sn, sh;
-        bin_trig_lds(twl, f, lgN, cs, sn, sh);
+        bin_trig_lds(twl, tw, f, lgN, cs, sn, sh);
         out[f] = kernel_power(q, cs, sn, sh);
     }
 }
@@ -1953,7 +1970,7 @@ __device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN)
     const int x = __builtin_amdgcn_readfirstlane(cx.sh->spx);
     double2 *e = cx.spc + (ll)x * cx.spc_ent;
     if (__builtin_amdgcn_readfirstlane(cx.sh->spf)) {
-        spec_fill(cx.p, h, lgN, e, cx.twl);
+        spec_fill(cx.p, h, lgN, e, cx.twl, cx.tw);
         sync_stores();
     }
     return e;
