@@ -1644,10 +1644,13 @@ __device__ __forceinline__ void fetch_args(const Pool &pl, int ji, JobArgs *sh)
 // Queue through which the wave that solves a small trapezoid hands its
 // direct-stepping correlations to the workgroup's other waves (all in LDS).
 // A frame has at most one outstanding correlation, kept in the job slot of
-// its stack depth until the frame has waited for it; tickets (numbered in
-// push order) say which slot to run next, so the unclaimed tickets never
-// outnumber the frames on the stack.
-#define WQ 16  // job slots = deepest stack; also the ticket ring size
+// its stack depth until the frame has waited for it.  A correlation longer
+// than one wave's segment is queued as one ticket per output segment, so
+// that the waves step its segments side by side; tickets (numbered in push
+// order) name a slot and a part, and a slot's count of parts left reaches
+// zero when its job is done.
+#define WQ 16   // job slots = deepest stack
+#define WQT 64  // ticket ring: at most WQ frames, few of them longer than one segment
 struct WJob {
     const double *src;
     double *dst;
@@ -1655,11 +1658,11 @@ struct WJob {
 };
 struct WQueue {
     WJob job[WQ];
-    int done[WQ];    // slot's job finished: done[slot] == its ticket + 1
-    int ticket[WQ];  // ticket k names slot ticket[k % WQ]
-    int head;        // next ticket to claim
-    int tail;        // tickets issued
-    int quit;        // the pushing wave has finished
+    int left[WQ];     // parts of the slot's job not yet finished
+    int ticket[WQT];  // ticket k: slot | part << 8 | parts << 16, at k % WQT
+    int head;         // next ticket to claim
+    int tail;         // tickets issued
+    int quit;         // the pushing wave has finished
     int pad;
 };
 
@@ -2115,12 +2118,6 @@ __device__ __forceinline__ bool wave_sized(const Mp &d, const Tune &tn, ll nred,
 
 #define WGS __HIP_MEMORY_SCOPE_WORKGROUP
 
-// One direct-stepping correlation by the calling wave.
-__device__ __forceinline__ void run_direct(const Mp &d, const WJob &j)
-{
-    direct_part(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst, 0, 1);
-}
-
 // Claim the next unclaimed ticket (one wave; -1 if none).
 __device__ __forceinline__ int wq_claim(WQueue *q)
 {
@@ -2138,18 +2135,19 @@ __device__ __forceinline__ int wq_claim(WQueue *q)
     return __builtin_amdgcn_readfirstlane(k);
 }
 
-// Run the job of claimed ticket k and mark it done (its global writes complete first).
+// Run the part of claimed ticket k and count it done (its global writes complete first).
 __device__ __forceinline__ void wq_run(const Mp &d, WQueue *q, int k)
 {
-    const int slot = __builtin_amdgcn_readfirstlane(q->ticket[k % WQ]);
+    const int e = __builtin_amdgcn_readfirstlane(q->ticket[k % WQT]);
+    const int slot = e & 255, part = (e >> 8) & 255, parts = e >> 16;
     WJob j = q->job[slot];
     j.n_in = uni(j.n_in);
     j.h = uni(j.h);
     j.out_off = uni(j.out_off);
     j.n_out = uni(j.n_out);
-    run_direct(d, j);
+    direct_part(d, j.src, j.n_in, j.h, j.out_off, j.n_out, j.dst, part, parts);
     wave_sync();
-    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&q->done[slot], k + 1, __ATOMIC_RELEASE, WGS);
+    if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_sub(&q->left[slot], 1, __ATOMIC_RELEASE, WGS);
 }
 
 // A helper wave of a small-trapezoid solve: run queued correlations until the
@@ -2174,28 +2172,40 @@ __device__ __forceinline__ void wq_worker(const Mp &d, WQueue *q, ll timeout_tic
     }
 }
 
-// Push the job of stack slot `slot` (the solving wave); returns its ticket.
-__device__ __forceinline__ int wq_push(WQueue *q, int slot, const WJob &j, int *tail)
+// Push the job of stack slot `slot` (the solving wave); returns its first
+// ticket.  A lattice job gets one ticket per output segment while the ring
+// has room for them (else one ticket that steps every segment); a BSM job
+// keeps one ticket, since its segments overlap by a halo on both sides and
+// its waves are kept busy by the many short correlations of the cone.
+__device__ __forceinline__ int wq_push(const Mp &d, WQueue *q, int slot, const WJob &j, int *tail)
 {
     const int k = *tail;
+    int parts = (d.model == BSM) ? 1 : direct_nseg(d, j.n_in, j.h, j.n_out);
+    if (parts > 1) {
+        int hd = 0;
+        if ((threadIdx.x & 63) == 0) hd = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, WGS);
+        hd = __builtin_amdgcn_readfirstlane(hd);
+        if (k - hd + parts > WQT) parts = 1;
+    }
     if ((threadIdx.x & 63) == 0) {
         q->job[slot] = j;
-        q->ticket[k % WQ] = slot;
+        q->left[slot] = parts;
+        for (int p = 0; p < parts; ++p) q->ticket[(k + p) % WQT] = slot | (p << 8) | (parts << 16);
     }
     wave_sync();  // the entry and this wave's row writes precede the publication
-    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&q->tail, k + 1, __ATOMIC_RELEASE, WGS);
-    *tail = k + 1;
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&q->tail, k + parts, __ATOMIC_RELEASE, WGS);
+    *tail = k + parts;
     return k;
 }
 
-// Wait for the job of slot `slot`, ticket k (the solving wave), running
-// unclaimed jobs meanwhile.
-__device__ __forceinline__ bool wq_wait(const Mp &d, WQueue *q, int slot, int k, ll timeout_ticks, Stats *st)
+// Wait for the job of slot `slot` (the solving wave), running unclaimed
+// tickets meanwhile.
+__device__ __forceinline__ bool wq_wait(const Mp &d, WQueue *q, int slot, ll timeout_ticks, Stats *st)
 {
     const ll t0 = now_ticks();
     for (;;) {
         int fin = 0;
-        if ((threadIdx.x & 63) == 0) fin = __hip_atomic_load(&q->done[slot], __ATOMIC_ACQUIRE, WGS) == k + 1;
+        if ((threadIdx.x & 63) == 0) fin = __hip_atomic_load(&q->left[slot], __ATOMIC_ACQUIRE, WGS) == 0;
         if (__builtin_amdgcn_readfirstlane(fin)) return true;
         const int c = wq_claim(q);
         if (c >= 0) {
@@ -2271,7 +2281,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
         // the frame's pending correlation (job index + 1 in soff) must be done
         // before its next stage reads its output
         if (fr.soff > 0) {
-            if (!wq_wait(d, q, sp, (int)fr.soff - 1, timeout, cx.st)) {
+            if (!wq_wait(d, q, sp, timeout, cx.st)) {
                 e = DEV_TIMEOUT;
                 break;
             }
@@ -2380,7 +2390,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             j.h = ch;
             j.out_off = coff;
             j.n_out = cout;
-            fr.soff = wq_push(q, sp, j, &tail) + 1;
+            fr.soff = wq_push(d, q, sp, j, &tail) + 1;
             if (l == 0) {
                 const int lg = ceil_log2(cn);
                 n_conv += 1;
@@ -2414,10 +2424,10 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     }
     if (e != DEV_OK && e != DEV_TIMEOUT) {
         // finish the outstanding jobs of this frame and of its ancestors
-        bool ok = fr.soff <= 0 || wq_wait(d, q, sp, (int)fr.soff - 1, timeout, cx.st);
+        bool ok = fr.soff <= 0 || wq_wait(d, q, sp, timeout, cx.st);
         for (int k = sp - 1; ok && k >= 0; --k) {
             const ll so = uni(wstk[k].soff);
-            if (so > 0) ok = wq_wait(d, q, k, (int)so - 1, timeout, cx.st);
+            if (so > 0) ok = wq_wait(d, q, k, timeout, cx.st);
         }
     }
     if (l == 0) {
@@ -2634,7 +2644,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
                 q->head = 0;
                 q->tail = 0;
                 q->quit = 0;
-                for (int k = 0; k < WQ; ++k) q->done[k] = -1;
+                for (int k = 0; k < WQ; ++k) q->left[k] = 0;
             }
             __syncthreads();
             if (tid < 64) {
