@@ -314,6 +314,8 @@ typedef struct {
                                longer ones as four-step transforms of 2048-point rows (11 or 12) */
     int32_t radix_lg;       /* FP64 LDS butterfly passes of radix 2^radix_lg (2 or 3) */
     int64_t timeout_ms;     /* a wait longer than this aborts the launch: its options price NaN (> 0) */
+    int64_t timeout_us;     /* > 0: the same deadline in microseconds, in place of timeout_ms (callers that
+                               need one below a millisecond); 0: timeout_ms applies */
 } aop_tuning;
 aop_status aop_ctx_get_tuning(const aop_ctx *ctx, aop_tuning *out);
 /* Returns AOP_EINVAL (and keeps the old tuning) for out-of-range fields. */

@@ -43,7 +43,7 @@ class AopTuning(ctypes.Structure):
                 ("direct_max_h", ctypes.c_int32), ("direct_max_n", ctypes.c_int32),
                 ("helper_idle_us", ctypes.c_int32), ("late_pub_min_lg", ctypes.c_int32),
                 ("late_after_pct", ctypes.c_int32), ("lds_max_lg", ctypes.c_int32), ("radix_lg", ctypes.c_int32),
-                ("timeout_ms", ctypes.c_int64)]
+                ("timeout_ms", ctypes.c_int64), ("timeout_us", ctypes.c_int64)]
 
 
 class AopError(RuntimeError):

@@ -314,7 +314,8 @@ Tune make_tune(const aop_tuning &t, double tick_hz, int32_t workgroups)
     tune.lds_lg64 = t.lds_max_lg;
     tune.radix = t.radix_lg;
     tune.late_after = t.late_after_pct;  // a percentage until the launch converts it
-    tune.timeout_ticks = (int64_t)(1e-3 * (double)t.timeout_ms * tick_hz);
+    tune.timeout_ticks = t.timeout_us > 0 ? (int64_t)(1e-6 * (double)t.timeout_us * tick_hz)
+                                          : (int64_t)(1e-3 * (double)t.timeout_ms * tick_hz);
     tune.idle_ticks = (int64_t)(1e-6 * (double)t.helper_idle_us * tick_hz);
     return tune;
 }
@@ -324,7 +325,8 @@ bool tuning_valid(const aop_tuning &u)
     return u.workgroups >= 1 && u.workgroups <= MAX_WG && u.pub_min_lg >= 1 && u.pub_min_lg <= 30 &&
            u.direct_max_h >= 0 && u.direct_max_h <= DIRECT_MAX_H && u.direct_max_n >= 0 && u.direct_max_n <= DIRECT_MAX_N && u.helper_idle_us >= 1 &&
            u.late_pub_min_lg >= 0 && u.late_pub_min_lg <= 30 && u.late_after_pct >= 0 && u.late_after_pct <= 100 &&
-           u.timeout_ms > 0 && u.timeout_ms <= 3600000 && (u.lds_max_lg == 11 || u.lds_max_lg == 12) &&
+           u.timeout_ms > 0 && u.timeout_ms <= 3600000 && u.timeout_us >= 0 && u.timeout_us <= 3600000000ll &&
+           (u.lds_max_lg == 11 || u.lds_max_lg == 12) &&
            (u.radix_lg == 2 || u.radix_lg == 3);
 }
 
@@ -409,6 +411,7 @@ aop_status aop_ctx_create(int device, double lambda, void *d_twiddles, size_t tw
     ctx->tuning.late_pub_min_lg = 10;
     ctx->tuning.late_after_pct = 50;
     ctx->tuning.timeout_ms = 30000;
+    ctx->tuning.timeout_us = 0;
     ctx->tuning.lds_max_lg = 12;
     ctx->tuning.radix_lg = 3;
     if (hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess ||

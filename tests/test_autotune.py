@@ -29,7 +29,7 @@ def test_candidates_cover_the_tuned_fields():
     keys = set(autotune.SCHEDULE_KEYS)
     assert all(set(dict(autotune.SCHEDULE_DEFAULTS, **c)) == keys for c in autotune.CANDIDATES)
     assert keys <= {"workgroups", "pub_min_lg", "pub_direct", "direct_max_h", "direct_max_n", "helper_idle_us",
-                    "timeout_ms", "lds_max_lg", "radix_lg"}
+                    "timeout_ms", "timeout_us", "lds_max_lg", "radix_lg"}
     # FFT schedules are among the candidates: LDS transform size and pass radix
     assert {dict(autotune.SCHEDULE_DEFAULTS, **c)["lds_max_lg"] for c in autotune.CANDIDATES} == {11, 12}
     assert {dict(autotune.SCHEDULE_DEFAULTS, **c)["radix_lg"] for c in autotune.CANDIDATES} == {2, 3}
