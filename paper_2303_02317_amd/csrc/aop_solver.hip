@@ -515,16 +515,23 @@ __device__ __forceinline__ double2 twiddle_n(ll m, int lgN)
     sincospi((double)(2 * m) / (double)(ll(1) << lgN), &sv, &cv);
     return make_double2(cv, -sv);
 }
-// The same from the tables: m = m_hi 2^s + m_lo (N = 4096 * 2^s) gives
-// e^{-2 pi i m_hi / 4096} (LDS table) times e^{-2 pi i m_lo / N} (a stretch of
-// 2^s entries of the 2^22-point global table, which stays in cache).
-__device__ __forceinline__ double2 twiddle_tab(ll m, int lgN, const double2 *__restrict__ tw, const double2 *twl)
+// Four-step column twiddles from tables: for N = 4096 * 2^s, m = m_hi 2^s +
+// m_lo gives e^{-2 pi i m_hi / 4096} (the LDS trig table) times
+// e^{-2 pi i m_lo / N}, m_lo < 2^s, from the tile's small table twx (copied
+// from the 2^22-point global table into LDS above the tile's values).
+#define TWX_OFF 2560
+static_assert(TWX_OFF >= NLDS + NLDS / 8 && TWX_OFF + (1 << (LG_TW - LG_NLDS - 1)) <= NLDS64 + NLDS64 / 8,
+              "the small twiddle table lies above a column tile's padded values, inside the FP64 LDS buffer");
+__device__ __forceinline__ void fill_twx(double2 *twx, int lgN, const double2 *__restrict__ tw)
 {
-    if (lgN <= LG_NLDS + 1) return twl_at(twl, (int)(m << (LG_NLDS + 1 - lgN)));
+    const int s = lgN - (LG_NLDS + 1);
+    for (int r = threadIdx.x; r < (1 << s); r += WG) twx[r] = tw[(ll)r << (LG_TW - lgN)];
+}
+__device__ __forceinline__ double2 twiddle_col(ll m, int lgN, const double2 *twl, const double2 *twx)
+{
     const int s = lgN - (LG_NLDS + 1);
     const double2 hi = twl_at(twl, (int)(m >> s));
-    const double2 lo = tw[(m & ((ll(1) << s) - 1)) << (LG_TW - lgN)];
-    return cmul(hi, lo);
+    return s == 0 ? hi : cmul(hi, twx[m & ((ll(1) << s) - 1)]);
 }
 
 // cs, sn: cos and sin of theta; sh: +-sin(theta/2) (only its square is used).
@@ -683,12 +690,14 @@ __device__ __forceinline__ void tile_col_fwd(const JobArgs &j, int tile, double2
             const int c = t & (C - 1), n1 = t >> lgC;
             lds[px(c * N1 + n1)].x = tilt_in(lds[px(c * N1 + n1)].x, j.beta, (ll)n1 * N2 + n20 + c, j.tc);
         }
+    double2 *twx = lds + TWX_OFF;
+    fill_twx(twx, lgN, tw);
     __syncthreads();
     lds_dif(lds, lg1, C, twl, j.radix);
     for (int t = tid; t < NLDS; t += WG) {
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = twiddle_tab((n2 * k1) & (N - 1), lgN, tw, twl);
+        const double2 w = twiddle_col((n2 * k1) & (N - 1), lgN, twl, twx);
         j.scr[(ll)p1 * N2 + n2] = cmul(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
@@ -757,10 +766,13 @@ __device__ __forceinline__ void tile_col_inv(const JobArgs &j, int tile, double2
         const int c = t & (C - 1), p1 = t >> lgC;
         lds[px(c * N1 + p1)] = j.scr[(ll)p1 * N2 + n20 + c];
     }
+    double2 *twx = lds + TWX_OFF;
+    fill_twx(twx, lgN, tw);
+    __syncthreads();
     for (int t = tid; t < NLDS; t += WG) {  // the same elements, in the same threads
         const int c = t & (C - 1), p1 = t >> lgC;
         const ll k1 = bitrev(p1, lg1), n2 = n20 + c;
-        const double2 w = twiddle_tab((n2 * k1) & (N - 1), lgN, tw, twl);
+        const double2 w = twiddle_col((n2 * k1) & (N - 1), lgN, twl, twx);
         lds[px(c * N1 + p1)] = cmulc(lds[px(c * N1 + p1)], w);
     }
     __syncthreads();
