@@ -35,8 +35,8 @@ namespace aop {
 #define NLDS64 4096  // FP64 transforms of up to this many points run whole in LDS (64 KB)
 #define LG_NLDS64 12
 #define MAXD 48    // recursion depth bound (log2 of 2^22 plus slack)
-#define BAND 64    // cells held by the BSM and Bermudan band walkers (one per lane)
-#define BAND_LAT 128  // cells held by the lattice band walker (two per lane)
+#define BAND 64    // cells held by the Bermudan band walker (one per lane)
+#define BAND2 128  // cells held by the lattice and BSM band walkers (two per lane)
 
 typedef long long ll;
 
@@ -63,11 +63,11 @@ __device__ __forceinline__ Mp make_mp(const Desc &d)
     return p;
 }
 
-// Cells of a band leaf: the lattice walker holds two per lane, the BSM and
-// Bermudan walkers one.
+// Cells of a band leaf: the lattice and BSM walkers hold two per lane, the
+// Bermudan walker one.
 __device__ __forceinline__ ll band_width(const Mp &p)
 {
-    return (p.model != BSM && p.ex_every <= 1) ? BAND_LAT : BAND;
+    return (p.model == BSM || p.ex_every <= 1) ? BAND2 : BAND;
 }
 
 // Wave-uniform copy of a value that is uniform by construction.
@@ -1196,7 +1196,7 @@ __device__ __forceinline__ void lat_step(double &gA, double &gB, double &eA, dou
 
 // Rows i0-1 .. i0-h of a lattice (binomial: row i has columns 0..i, cell j
 // reads j and j+1; trinomial: columns 0..2i, cell j reads j, j+1, j+2) from
-// row i0, whose red cells are [c0, b] (b - c0 + 1 <= BAND_LAT); columns >= c0
+// row i0, whose red cells are [c0, b] (b - c0 + 1 <= BAND2); columns >= c0
 // only, two per lane.  Writes the red cells of row i0-h to dst, the boundary
 // of each row to bnd (may be NULL); returns the last red column of row i0-h.
 // *v0 receives the final value of column c0.
@@ -1239,11 +1239,11 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
         const int itop = i0 - k0;  // row above the block
         const double eA0 = S * exp((double)(cs * jA - itop) * a) - K;
         const double eB0 = S * exp((double)(cs * jB - itop) * a) - K;
-        const double f10 = S * exp((double)(cs * (c0 + BAND_LAT) - itop) * a) - K;
+        const double f10 = S * exp((double)(cs * (c0 + BAND2) - itop) * a) - K;
         const double f20 = TRI ? fma(f10, u, ku) : 0.0;
         const int L0 = bc - c0;
         bool done = false;
-        if (wr * (itop - nb) - c0 >= BAND_LAT - 1 && L0 >= 0 && L0 <= BAND_LAT - 1) {
+        if (wr * (itop - nb) - c0 >= BAND2 - 1 && L0 >= 0 && L0 <= BAND2 - 1) {
             double ga = gA, gb = gB, ea = eA0, eb = eB0, f1 = f10, f2 = f20;
             int na = 0, nbb = 0, la = -1, lb = -1;
             bool rA, rB;
@@ -1311,7 +1311,7 @@ __device__ __forceinline__ ll band_lat(Mp p, ll i0_, ll c0_, ll h_, ll b_, const
                     bc = c0 + x;
                 } else {
                     const int lc = bc - c0;
-                    if (lc >= 0 && lc < BAND_LAT) bc -= ((((lc & 1) ? mB : mA) >> (lc >> 1)) & 1ull) ? 0 : 1;
+                    if (lc >= 0 && lc < BAND2) bc -= ((((lc & 1) ? mB : mA) >> (lc >> 1)) & 1ull) ? 0 : 1;
                 }
                 q = (l == r) ? bc : q;
             }
@@ -1388,31 +1388,39 @@ __device__ __forceinline__ ll band_tri(Mp p, ll i0, ll c0, ll h, ll b, const dou
     return band_lat<true>(p, i0, c0, h, b, src, dst, bnd, v0);
 }
 
-// One step of the BSM band: the lane's cell moves one to the left; the new
-// cell k needs old cells k-1, k, k+1 = old lanes l-2, l-1, l, and lane 0
-// takes exercise values for the cells left of the band.  Returns whether the
-// new cell is continuation (not exercise).
-__device__ __forceinline__ bool bsm_step(double &v, double &x, double ud, double w0, double w1, double w2)
+// One step of the BSM band, two cells per lane: lane l holds positions 2l (A)
+// and 2l+1 (B) of the band, which moves one cell to the left per step, so the
+// new A cell needs old positions 2l-2, 2l-1, 2l (the previous lane's A and B,
+// its own A) and the new B cell old positions 2l-1, 2l, 2l+1; lane 0 takes
+// exercise values for the cells left of the band.  xA is e^{s} of the lane's
+// A cell (its new B cell is its old A cell).  rA, rB: whether the new cells
+// are continuation (not exercise).
+__device__ __forceinline__ void bsm_step(double &vA, double &vB, double &xA, double ud, double w0, double w1,
+                                         double w2, bool &rA, bool &rB)
 {
-    x *= ud;                   // e^{s_k} of the lane's new cell
-    const double xm = x * ud;  // e^{s_{k-1}}
-    const double g = 1.0 - x;
-    const double vm1 = dpp_up1(v, g);
-    const double vm2 = dpp_up1(vm1, 1.0 - xm);
-    const double cont = fma(w2, v, fma(w1, vm1, w0 * vm2));
-    v = vmax_f64(cont, g);
-    return !(g > cont);
+    const double xB = xA;
+    xA *= ud;
+    const double gA = 1.0 - xA, gB = 1.0 - xB;
+    const double pA = dpp_up1(vA, 1.0 - xA * ud);  // old position 2l-2 (lane 0: the cell left of the new A)
+    const double pB = dpp_up1(vB, gA);             // old position 2l-1 (lane 0: the new A cell itself)
+    const double cA = fma(w2, vA, fma(w1, pB, w0 * pA));
+    const double cB = fma(w2, vB, fma(w1, vA, w0 * pB));
+    vA = vmax_f64(cA, gA);
+    vB = vmax_f64(cB, gB);
+    rA = !(gA > cA);
+    rB = !(gB > cB);
 }
 
 // BSM put: steps n0+1 .. n0+h from step n0, whose exercise cells are k <= f
 // and whose continuation cells [f+1, R0] are read from src (absolute k).  The
-// band's right edge starts at R0 and moves left one cell per step (the
-// dependency cone), its left part stays inside the exercise region (needs
-// R0 - f <= 62).  Writes the red cells of step n0+h, up to R0-h, to dst and
-// returns the last exercise offset of step n0+h.  *vr receives the value of
-// the rightmost cell (the apex when R0 - h = 0).  Here the boundary is the
-// last exercise (green) cell; it stays or moves one cell left per step
-// (Theorem 4.2).
+// band (128 cells, two per lane) has its right edge at R0 and moves left one
+// cell per step (the dependency cone); its left part stays inside the
+// exercise region (needs R0 - f <= 126).  Writes the red cells of step n0+h,
+// up to R0-h, to dst and returns the last exercise offset of step n0+h.  *vr
+// receives the value of the rightmost cell (the apex when R0 - h = 0).  Here
+// the boundary is the last exercise (green) cell; it stays or moves one cell
+// left per step (Theorem 4.2), so in band positions (which move left with the
+// band) the exercise prefix grows by 0 or 1 position per step.
 __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const double *src, double *dst,
                                        ll *bnd, double *vr)
 {
@@ -1422,48 +1430,62 @@ __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const
     const int T = (int)p.T;
     const double w0 = p.w0, w1 = p.w1, w2 = p.w2, s0 = p.s0, ds = p.a;
     const double ud = exp(-ds);  // e^{-ds}: one cell to the left
-    int base = R0 - 63;
-    int k = base + l;
-    double v = (k <= f) ? 1.0 - exp(s0 + (double)k * ds) : src[k];
+    int base = R0 - (BAND2 - 1);
+    const int kA = base + 2 * l, kB = kA + 1;
+    double vA = (kA <= f) ? 1.0 - exp(s0 + (double)kA * ds) : src[kA];
+    double vB = (kB <= f) ? 1.0 - exp(s0 + (double)kB * ds) : src[kB];
     int fc = f;
     for (int t0 = 0; t0 < h; t0 += 64) {
         const int nb = (h - t0) < 64 ? (h - t0) : 64;
-        const int base0 = base;                           // band base before the block
-        const double x0 = exp(s0 + (double)(base0 + l) * ds);  // e^{s_k} of the lane's cell before the block
-        // Fast form (as band_lat): per lane the number of continuation rows and
-        // the last one.  Row r of the block has lane 0 at cell base0 - 1 - r, so
-        // the exercise cells (lanes 0 .. G_r - 1) grow by 0 or 1 lanes per row
-        // (Theorem 4.2: the boundary stays or moves one cell left).
+        const int base0 = base;                                     // band base before the block
+        const double x0 = exp(s0 + (double)(base0 + 2 * l) * ds);  // e^{s} of the lane's A cell before the block
+        // Fast form (as band_lat): per cell the number of continuation rows and
+        // the last one.  Row r of the block has position 0 at cell base0 - 1 - r,
+        // so the exercise positions (0 .. G_r - 1) grow by 0 or 1 per row.
         bool done = false;
         {
-            double vv = v, x = x0;
-            int cnt = 0, lastr = -1;
+            double va = vA, vb = vB, x = x0;
+            int na = 0, nbb = 0, la = -1, lb = -1;
+            bool rA, rB;
             if (nb == 64) {
 #pragma unroll
                 for (int r = 0; r < 64; ++r) {
-                    const bool red = bsm_step(vv, x, ud, w0, w1, w2);
-                    cnt += red ? 1 : 0;
-                    lastr = red ? r : lastr;
+                    bsm_step(va, vb, x, ud, w0, w1, w2, rA, rB);
+                    na += rA ? 1 : 0;
+                    la = rA ? r : la;
+                    nbb += rB ? 1 : 0;
+                    lb = rB ? r : lb;
                 }
             } else {
                 for (int r = 0; r < nb; ++r) {
-                    const bool red = bsm_step(vv, x, ud, w0, w1, w2);
-                    cnt += red ? 1 : 0;
-                    lastr = red ? r : lastr;
+                    bsm_step(va, vb, x, ud, w0, w1, w2, rA, rB);
+                    na += rA ? 1 : 0;
+                    la = rA ? r : la;
+                    nbb += rB ? 1 : 0;
+                    lb = rB ? r : lb;
                 }
             }
-            const int nxt = __shfl_down(cnt, 1, 64);
-            const bool prefix = (cnt == 0) || (lastr == cnt - 1);
-            const bool shape = (l == 63) || cnt < nxt || (cnt == nxt && (cnt == 0 || cnt == nb));
-            const int g0 = (int)__popcll(__ballot(cnt == 0));  // exercise lanes of the first row
+            // counts of the next positions: 2l+1 is this lane's B, 2l+2 the next lane's A
+            const int nxtA = nbb;
+            const int nxtB = __shfl_down(na, 1, 64);
+            const bool okA = ((na == 0) || (la == na - 1)) &&
+                             (na < nxtA || (na == nxtA && (na == 0 || na == nb)));
+            const bool okB = ((nbb == 0) || (lb == nbb - 1)) &&
+                             (l == 63 || nbb < nxtB || (nbb == nxtB && (nbb == 0 || nbb == nb)));
+            const int g0 = (int)__popcll(__ballot(na == 0)) + (int)__popcll(__ballot(nbb == 0));  // exercise positions of the first row
             const int gin = fc - base0 + 1;
-            if (__ballot(!(prefix && shape)) == 0ull && g0 >= 1 && (g0 == gin || g0 == gin + 1)) {
-                v = vv;
-                const int glast = 64 - (int)__popcll(__ballot(cnt == nb));
+            if (__ballot(!(okA && okB)) == 0ull && g0 >= 1 && (g0 == gin || g0 == gin + 1)) {
+                vA = va;
+                vB = vb;
+                const int glast = BAND2 - (int)__popcll(__ballot(na == nb)) - (int)__popcll(__ballot(nbb == nb));
                 fc = base0 - nb + glast - 1;
                 if (bnd) {
+                    // lane r: row r's last exercise cell
                     int q = base0 - 1 - l - 1;
-                    for (int m = 0; m < 64; ++m) q += (__builtin_amdgcn_readlane(cnt, m) <= l) ? 1 : 0;
+                    for (int m = 0; m < 64; ++m) {
+                        q += (__builtin_amdgcn_readlane(na, m) <= l) ? 1 : 0;
+                        q += (__builtin_amdgcn_readlane(nbb, m) <= l) ? 1 : 0;
+                    }
                     if (l < nb) {
                         const int n = n0 + t0 + 1 + l;
                         bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
@@ -1473,17 +1495,18 @@ __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const
             }
         }
         if (!done) {
+            // the one-cell rule row by row: the previous boundary cell still
+            // exercise, it stays; continuation, the boundary moves left by one
             double x = x0;
-            unsigned mlo = 0, mhi = 0;
+            int q = 0;
             for (int r = 0; r < nb; ++r) {
-                const bool red = bsm_step(v, x, ud, w0, w1, w2);
-                const unsigned long long m = __ballot(!red);  // exercise lanes
-                mlo = writelane(mlo, (unsigned)m, r);
-                mhi = writelane(mhi, (unsigned)(m >> 32), r);
+                bool rA, rB;
+                bsm_step(vA, vB, x, ud, w0, w1, w2, rA, rB);
+                const unsigned long long mA = __ballot(!rA), mB = __ballot(!rB);  // exercise positions
+                const int pos = fc - (base0 - 1 - r);  // the previous boundary cell's position in this row
+                if (pos >= 0 && pos < BAND2) fc -= ((((pos & 1) ? mB : mA) >> (pos >> 1)) & 1ull) ? 0 : 1;
+                q = (l == r) ? fc : q;
             }
-            int q;
-            // row r of the block has lane 0 at cell base0 - 1 - r
-            fc = resolve_block<false>(mlo, mhi, nb, fc, base0 - 1, -1, 0, &q, 0);
             if (bnd && l < nb) {
                 const int n = n0 + t0 + 1 + l;
                 bnd[n] = (q < -(T - n)) ? BSM_NONE : (ll)(q > T - n ? T - n : q);
@@ -1491,9 +1514,10 @@ __device__ __forceinline__ ll band_bsm(Mp p, ll n0_, ll f_, ll h_, ll R0_, const
         }
         base -= nb;
     }
-    k = base + l;
-    if (k > fc && k <= R0 - h) dst[k] = v;
-    if (vr && l == 63) *vr = v;
+    const int ka = base + 2 * l, kb = ka + 1;
+    if (ka > fc && ka <= R0 - h) dst[ka] = vA;
+    if (kb > fc && kb <= R0 - h) dst[kb] = vB;
+    if (vr && l == 63) *vr = vB;
     return fc;
 }
 
@@ -2282,7 +2306,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
     };
     // leaf test and its range checks (lattice: red cells [c0, b]; BSM: centred on c0)
     auto is_leaf = [&](const Frame &f) -> bool {
-        return (d.model != BSM) ? (f.b - f.c0 + 1 <= bw) : (f.h <= (BAND - 2) / 2);
+        return (d.model != BSM) ? (f.b - f.c0 + 1 <= bw) : (f.h <= (bw - 2) / 2);
     };
     auto leaf_ok = [&](const Frame &f) -> bool {
         return (d.model != BSM) ? (in_ws(cx, f.src, f.c0, f.b) && in_ws(cx, f.dst, f.c0, f.c0 + bw - 1))
@@ -2351,7 +2375,7 @@ __device__ __forceinline__ ll wave_solve(const Ctx &cx, Frame root, Frame *wstk,
             const ll n = fr.r0, f = fr.c0, h = fr.h;
             const ll h1 = h / 2, h2 = h - h1;
             if (fr.stage == 0) {
-                if (h <= (BAND - 2) / 2) {  // only a root can be a leaf
+                if (h <= (bw - 2) / 2) {  // only a root can be a leaf
                     if (!leaf_ok(fr)) e = DEV_RANGE;
                     else leaf = true;
                     pop = true;
@@ -2607,7 +2631,7 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             const ll n = fr.r0, f = fr.c0, h = fr.h;
             const ll h1 = h / 2, h2 = h - h1;
             if (fr.stage == 0) {
-                if (h <= (BAND - 2) / 2 || wave_sized(d, cx.tn, 2 * h, h)) {
+                if (h <= (BAND2 - 2) / 2 || wave_sized(d, cx.tn, 2 * h, h)) {
                     leaf = true;  // wave 0 solves it alone
                     pop = true;
                 } else {
@@ -2949,7 +2973,7 @@ __device__ __forceinline__ double drive_bsm(const Ctx &cx, double *rowA, double 
             return d.K * ex_bsm(d, 0);
         }
         const ll w = R - f;
-        if (w <= BAND - 2) {  // the band walks the leftover cone to the apex
+        if (w <= BAND2 - 2) {  // the band walks the leftover cone to the apex
             const ll tb = clk();
             if (tid < 64) band_bsm(d, n, f, T - n, R, src, dst, cx.bnd, val_sh);
             __syncthreads();

@@ -13,7 +13,7 @@ import math
 
 import numpy as np
 
-BAND = 64        # BSM band walker: one cell per lane
+BAND = 128       # BSM band walker: two cells per lane
 BAND_LAT = 128   # lattice band walker: two cells per lane
 BINOMIAL, TRINOMIAL, BSM = 0, 1, 2
 NONE = np.iinfo(np.int64).min
@@ -187,7 +187,7 @@ class Model:
 
     def band_bsm(self, n0, f, h, R0, src: Buf, dst: Buf):
         d, T = self.d, self.T
-        base = R0 - 63
+        base = R0 - (BAND - 1)
         k = base + np.arange(BAND)
         v = ex_bsm(d, k)
         if R0 >= f + 1:
