@@ -16,9 +16,11 @@ hold only the first k options of the 64 (stated in the file as
 
 Options are priced in parallel, one per thread; each finished option is
 cached under ``--cache`` so that an interrupted run resumes where it stopped.
+``--partial`` prices nothing: it writes each file with the longest run of
+options 0, 1, ... found in the cache, where that extends the stored file.
 
 Usage: python tests/golden/make_golden.py [--threads N] [--only name ...]
-                                          [--cache DIR]
+                                          [--cache DIR] [--partial]
        python tests/golden/make_golden.py --european   (European lattice sums)
 """
 from __future__ import annotations
@@ -77,7 +79,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=len(os.sched_getaffinity(0)))
     ap.add_argument("--only", nargs="*", default=None)
-    ap.add_argument("--cache", default=os.path.join(ROOT, "_work", "golden_cache"))
+    ap.add_argument("--cache", default=os.path.join(HERE, "cache"))
+    ap.add_argument("--partial", action="store_true")
     args = ap.parse_args()
     oracle.build()
     os.makedirs(args.cache, exist_ok=True)
@@ -98,6 +101,22 @@ def main():
                 rec = json.loads(line)
                 done[rec["index"]] = rec["record"]
         opts = inputs.batch(cfg, log2T, 64, model)[:n]
+        if args.partial:
+            k = 0
+            while k < n and k in done:
+                k += 1
+            have = json.load(open(path)).get("n_options", 0) if os.path.exists(path) else 0
+            if k > have:
+                assert all(done[i]["params"] == opts[i] for i in range(k))
+                doc = dict(model=model, config=cfg, log2T=log2T, T=1 << log2T, n_options=k,
+                           seed=[cfg, log2T], lam=oracle.DEFAULT_LAMBDA, threads=args.threads,
+                           wall_seconds=sum(done[i]["seconds"] for i in range(k)),
+                           options=[done[i] for i in range(k)])
+                with open(path + ".tmp", "w") as f:
+                    json.dump(doc, f, indent=1)
+                os.replace(path + ".tmp", path)
+                print("wrote", fname, "with the first", k, "options", flush=True)
+            continue
         todo = [k for k in range(n) if k not in done]
         t0 = time.time()
 
