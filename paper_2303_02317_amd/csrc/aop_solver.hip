@@ -604,7 +604,8 @@ struct JobArgs {
     ll n_in, h, out_off, n_out;
     double beta, tc;
     int desc, lgN, kind, ntile, nph, prec;  // prec: 0 FP64, 1 split FP32
-    int radix, pad;                          // FP64 LDS passes of radix 2^radix (2 or 3)
+    int radix;                               // FP64 LDS passes of radix 2^radix (2 or 3)
+    int cached;                              // K_LDS: 1 if scr holds the job's kernel spectrum (bins 0 .. N/2)
 };
 static_assert(sizeof(JobArgs) == 104, "job arguments are 104 bytes");
 
@@ -622,6 +623,7 @@ __device__ __forceinline__ JobArgs uni_args(JobArgs a)
     u.nph = __builtin_amdgcn_readfirstlane(a.nph);
     u.prec = __builtin_amdgcn_readfirstlane(a.prec);
     u.radix = __builtin_amdgcn_readfirstlane(a.radix);
+    u.cached = __builtin_amdgcn_readfirstlane(a.cached);
     return u;
 }
 
@@ -1708,6 +1710,8 @@ struct Shared {
     ll spk[SPC_E];  // spectrum cache keys (h << 8 | lgN), -1 empty
     int late, pad4[3];  // most of the launch's options are done: publish more (Tune::late_pub_lg)
     int spn, spx, spf, pad3;  // entries handed out; lookup result: entry, fill needed
+    int spin[SPC_E];          // published jobs reading each spectrum-cache entry (not replaced while > 0)
+    int sppub[JPW];           // cache entry read by each slot's published job, -1 none
     JobArgs args;          // arguments of the tile a helper claimed
     JobArgs jargs[JPW];    // arguments of each slot's pending job (driver)
     int pub[JPW];          // slot state: 0 idle, 1 published job pending, 2 private job pending
@@ -1722,7 +1726,8 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
 {
     if (a.desc < 0 || a.desc >= n || a.kind < K_DIRECT || a.kind > K_4STEP || a.lgN < 1 || a.lgN > LG_TW ||
         ph < 0 || ph >= a.nph || tile < 0 || tile >= a.ntile || a.n_in < 1 || a.n_out < 1 || a.n_in > (ll(1) << a.lgN) ||
-        a.prec < 0 || a.prec > 1 || (a.kind != K_DIRECT && a.prec != prec) || a.radix < 2 || a.radix > 3)
+        a.prec < 0 || a.prec > 1 || (a.kind != K_DIRECT && a.prec != prec) || a.radix < 2 || a.radix > 3 ||
+        a.cached < 0 || a.cached > 1 || (a.cached && (a.kind != K_LDS || a.lgN > SPC_LG)))
         return false;
     const Desc d = descs[a.desc];
     if (d.model < 0) return false;
@@ -1732,6 +1737,10 @@ __device__ __forceinline__ bool args_ok(const Desc *__restrict__ descs, ll n, co
     const char *d0 = (const char *)a.dst, *d1 = (const char *)(a.dst + a.n_out);
     if (s0 < lo || s1 > hi || d0 < lo || d1 > hi) return false;
     if (a.kind == K_LDS && a.lgN > lds_lg(prec)) return false;  // must fit the LDS buffer
+    if (a.cached) {  // a spectrum-cache entry: after the FFT scratch
+        const char *c0 = (const char *)a.scr, *c1 = (const char *)(a.scr + ((ll(1) << a.lgN) / 2 + 1));
+        if (c0 < hi || c1 > hi + 16 * SPC_E * spc_entry(d.nfft)) return false;
+    }
     if (a.kind == K_4STEP) {
         const char *c0 = (const char *)a.scr, *c1 = (const char *)(a.scr + (ll(1) << a.lgN));
         if (c0 < lo || c1 > hi || a.lgN <= LG_NLDS) return false;  // N1 >= 2 row tiles
@@ -1841,7 +1850,8 @@ __device__ void helper_loop(const Pool &pl, ll n, const Desc *__restrict__ descs
         const int ph = (msg >> 4) & 15, tile = msg >> 8;
         if (args_ok(descs, n, ws, a, ph, tile, PREC)) {
             const Mp p = make_mp(descs[a.desc]);
-            run_tile<PREC>(p, a, ph, tile, lds, tw, twl, twf);
+            run_tile<PREC>(p, a, ph, tile, lds, tw, twl, twf,
+                           (a.kind == K_LDS && a.cached) ? (const double2 *)a.scr : nullptr);
         } else if (tid == 0) {
             note_abort(pl, 1, ji, ((ll)ph << 32) | tile,
                        ((ll)a.kind << 48) | ((ll)a.nph << 40) | ((ll)a.lgN << 32) | (ll)(unsigned)a.ntile,
@@ -1917,6 +1927,9 @@ __device__ __forceinline__ void set_err(const Ctx &cx, int e)
     if (threadIdx.x == 0 && *cx.err_sh == 0) *cx.err_sh = e;
 }
 
+// The cached kernel spectrum of an h-step correlation of 2^lgN points (see below).
+__device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN, bool pin = false);
+
 // Correlate src[0..n_in) with the h-step kernel and write the window
 // [out_off, out_off + n_out) to dst (see the job description above), as the
 // pending job of slot `slot`, using the FFT scratch from offset soff.  Large
@@ -1947,7 +1960,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     a.kind = direct ? K_DIRECT : (lgN <= (PREC ? LG_NLDS : cx.tn.lds_lg64) ? K_LDS : K_4STEP);
     a.prec = direct ? 0 : PREC;  // direct stepping is always FP64
     a.radix = cx.tn.radix;
-    a.pad = 0;
+    a.cached = 0;
     a.nph = a.kind == K_4STEP ? 3 : 1;
     a.ntile = a.kind == K_4STEP ? (1 << (lgN - LG_NLDS)) : 1;
     const ll need = a.kind == K_4STEP ? (ll(1) << lgN) : 0;
@@ -1960,6 +1973,17 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
     // cheap: the drivers still running publish smaller correlations
     const int thr = (cx.tn.late_pub_lg > 0 && cx.sh->late) ? cx.tn.late_pub_lg : cx.tn.pub_min_lg;
     const bool publish = cx.pl.n_wg > 1 && (direct ? cx.tn.pub_direct != 0 : lgN >= thr);
+    // A published whole-LDS job of the FP64 path takes its kernel spectrum from
+    // the driver's cache (filled here on a miss), so that the tile reads it
+    // instead of evaluating it; the entry stays pinned until the job is done.
+    if (PREC == 0 && publish && a.kind == K_LDS && beta == 0.0 && lgN <= SPC_LG) {
+        const double2 *e = spec_get(cx, h, lgN, true);
+        if (e) {
+            a.scr = (double2 *)e;
+            a.cached = 1;
+            if (threadIdx.x == 0) cx.sh->sppub[slot] = cx.sh->spx;
+        }
+    }
     if (publish) sync_stores();  // the workgroup's writes of the input row precede the release below
     if (threadIdx.x == 0) {
         if (direct) cx.st->n_direct += 1;
@@ -1986,7 +2010,7 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
 
 // The cached kernel spectrum of an h-step correlation of 2^lgN points (all
 // threads call; filled on a miss, oldest entry replaced).
-__device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN)
+__device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN, bool pin)
 {
     static_assert(SPC_E <= 64, "one key per lane of wave 0");
     if (threadIdx.x < 64) {
@@ -1998,21 +2022,37 @@ __device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN)
             int x = hit ? 63 - __clzll(hit) : -1;
             cx.sh->spf = x < 0;
             if (x < 0) {
-                x = cx.sh->spn % SPC_E;
-                cx.sh->spn += 1;
-                cx.sh->spk[x] = key;
+                // the oldest entry that no outstanding published job reads
+                for (int k = 0; k < SPC_E && x < 0; ++k) {
+                    const int y = cx.sh->spn % SPC_E;
+                    cx.sh->spn += 1;
+                    if (cx.sh->spin[y] == 0) x = y;
+                }
+                if (x >= 0) cx.sh->spk[x] = key;
             }
+            if (pin && x >= 0) cx.sh->spin[x] += 1;
             cx.sh->spx = x;
         }
     }
     __syncthreads();
     const int x = __builtin_amdgcn_readfirstlane(cx.sh->spx);
+    if (x < 0) return nullptr;  // every entry is read by an outstanding job
     double2 *e = cx.spc + (ll)x * cx.spc_ent;
     if (__builtin_amdgcn_readfirstlane(cx.sh->spf)) {
         spec_fill(cx.p, h, lgN, e, cx.twl, cx.tw);
         sync_stores();
     }
     return e;
+}
+
+// The published job of `slot` no longer reads its spectrum-cache entry (thread 0).
+__device__ __forceinline__ void unpin_spec(const Ctx &cx, int slot)
+{
+    const int x = cx.sh->sppub[slot];
+    if (x >= 0) {
+        cx.sh->spin[x] -= 1;
+        cx.sh->sppub[slot] = -1;
+    }
 }
 
 // Finish the pending job of `slot`: a private job's tiles are computed here
@@ -2030,7 +2070,9 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
     // a private FP64 transform takes its kernel spectrum from the cache
     const bool cached = PREC == 0 && mode == 2 && a.kind != K_DIRECT && a.lgN <= SPC_LG &&
                         __builtin_amdgcn_readfirstlane(a.beta == 0.0 ? 1 : 0);
-    const double2 *spec = cached ? spec_get(cx, a.h, a.lgN) : nullptr;
+    // a published one may carry it (the driver's cache entry, pinned)
+    const double2 *spec = cached ? spec_get(cx, a.h, a.lgN)
+                                 : ((a.kind == K_LDS && a.cached) ? (const double2 *)a.scr : nullptr);
     const ll deadline = now_ticks() + cx.tn.timeout_ticks;
     ll work = 0;
     int nph = 0, nt = 0;  // private: next tile
@@ -2086,6 +2128,7 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
     }
     if (threadIdx.x == 0) {
         cx.sh->pub[slot] = 0;
+        unpin_spec(cx, slot);
         cx.st->cyc_tiles += work;
         cx.st->cyc_wait += clk() - t0 - work;
     }
@@ -2122,6 +2165,7 @@ __device__ __forceinline__ void drain(const Ctx &cx)
                 }
             }
             cx.sh->pub[slot] = 0;
+            unpin_spec(cx, slot);
         }
     }
     __syncthreads();
@@ -3049,7 +3093,11 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
     cx.sh = sh;
     cx.err_sh = err_sh;
     if (tid == 0) {
-        for (int k = 0; k < SPC_E; ++k) sh->spk[k] = -1;
+        for (int k = 0; k < SPC_E; ++k) {
+            sh->spk[k] = -1;
+            sh->spin[k] = 0;
+        }
+        for (int k = 0; k < JPW; ++k) sh->sppub[k] = -1;
         sh->spn = 0;
         sh->late = 0;
         *err_sh = 0;
