@@ -520,6 +520,11 @@ __device__ __forceinline__ double2 twiddle_n(ll m, int lgN)
 // e^{-2 pi i m_lo / N}, m_lo < 2^s, from the tile's small table twx (copied
 // from the 2^22-point global table into LDS above the tile's values).
 #define TWX_OFF 2560
+// Staging area of a private whole-LDS correlation's input (up to 2048
+// doubles), above the small twiddle table: see conv_submit.
+#define STG_OFF 3584
+static_assert(STG_OFF >= TWX_OFF + (1 << (LG_TW - LG_NLDS - 1)) && STG_OFF + NLDS / 2 <= NLDS64 + NLDS64 / 8,
+              "the staging area lies above the column tiles' table, inside the FP64 LDS buffer");
 static_assert(TWX_OFF >= NLDS + NLDS / 8 && TWX_OFF + (1 << (LG_TW - LG_NLDS - 1)) <= NLDS64 + NLDS64 / 8,
               "the small twiddle table lies above a column tile's padded values, inside the FP64 LDS buffer");
 __device__ __forceinline__ void fill_twx(double2 *twx, int lgN, const double2 *__restrict__ tw)
@@ -637,7 +642,16 @@ __device__ __forceinline__ void tile_lds(const Mp &p, const JobArgs &j, double2 
     const Spec q = make_spec(p, j.h, j.beta, 0.0);
     const int tid = threadIdx.x;
     // unrolled so that several global loads are in flight at once
-    if (j.beta == 0.0) {
+    if (j.cached & 2) {
+        // the input pairs were loaded into the staging area when the job was
+        // submitted (direct global-to-LDS loads): wait for them, then spread
+        const double *stg = (const double *)(lds + STG_OFF);
+        const ll staged = j.n_in & ~ll(1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int t = tid; t < N; t += WG)
+            lds[px(t)] = make_double2(t < staged ? stg[t] : (t < j.n_in ? j.src[t] : 0.0), 0.0);
+    } else if (j.beta == 0.0) {
 #pragma unroll 4
         for (int t = tid; t < N; t += WG) lds[px(t)] = make_double2(t < j.n_in ? j.src[t] : 0.0, 0.0);
     } else {
@@ -1938,7 +1952,8 @@ __device__ __forceinline__ const double2 *spec_get(const Ctx &cx, ll h, int lgN,
 // (complex elements) the job holds until then.
 template <int PREC>
 __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, const double *src, ll n_in, ll h,
-                                          ll out_off, ll n_out, double *dst, double beta = 0.0, double tc = 0.0)
+                                          ll out_off, ll n_out, double *dst, double beta = 0.0, double tc = 0.0,
+                                          bool stage = false)
 {
     if (n_out <= 0) return 0;
     count_conv(cx.st, n_in, n_out);
@@ -1985,6 +2000,26 @@ __device__ __forceinline__ ll conv_submit(const Ctx &cx, int slot, ll soff, cons
         }
     }
     if (publish) sync_stores();  // the workgroup's writes of the input row precede the release below
+    // A private FP64 whole-LDS job of up to 2048 points whose frame next
+    // solves a wave-level sub-trapezoid (which uses no FFT buffer) starts
+    // loading its input now, straight from global memory into the staging
+    // area of the LDS buffer, so that the loads complete while the
+    // sub-trapezoid is solved (pairs of doubles; an odd last element is read
+    // by the tile).
+    if (PREC == 0 && stage && !publish && a.kind == K_LDS && beta == 0.0 && lgN <= LG_NLDS) {
+        __syncthreads();  // the input row's writes by this workgroup precede the loads
+        double *stg = (double *)(cx.lds + STG_OFF);
+        const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const ll pairs = n_in >> 1;
+        for (int k = 0; k * WG < pairs; ++k) {
+            const ll pr = (ll)k * WG + w * 64 + l;  // pair of this lane
+            if (pr < pairs)
+                __builtin_amdgcn_global_load_lds((const void *)(src + 2 * pr),
+                                                 (void __attribute__((address_space(3))) *)(stg + 2 * ((ll)k * WG + w * 64)),
+                                                 16, 0, 0);
+        }
+        a.cached |= 2;
+    }
     if (threadIdx.x == 0) {
         if (direct) cx.st->n_direct += 1;
         else cx.st->n_fft += 1;
@@ -2072,7 +2107,7 @@ __device__ __forceinline__ void conv_wait(const Ctx &cx, int slot)
                         __builtin_amdgcn_readfirstlane(a.beta == 0.0 ? 1 : 0);
     // a published one may carry it (the driver's cache entry, pinned)
     const double2 *spec = cached ? spec_get(cx, a.h, a.lgN)
-                                 : ((a.kind == K_LDS && a.cached) ? (const double2 *)a.scr : nullptr);
+                                 : ((a.kind == K_LDS && (a.cached & 1)) ? (const double2 *)a.scr : nullptr);
     const ll deadline = now_ticks() + cx.tn.timeout_ticks;
     ll work = 0;
     int nph = 0, nt = 0;  // private: next tile
@@ -2743,8 +2778,16 @@ __device__ __forceinline__ ll solve_trapezoid(const Ctx &cx, Frame root, Frame *
             __syncthreads();
             result = *leaf_sh;
         }
-        if (e == DEV_OK && !pop && cout > 0)
-            child.soff = fr.soff + conv_submit<PREC>(cx, slot, fr.soff, csrc, cn, ch, coff, cout, cdst);
+        if (e == DEV_OK && !pop && cout > 0) {
+            // the child is solved at wave level (no FFT tile runs before this
+            // correlation is waited for): its input may be staged in LDS
+            const bool child_wave = (d.model != BSM)
+                                        ? (child.b - child.c0 + 1 <= band_width(d) ||
+                                           (kstep <= BAND && wave_sized(d, cx.tn, child.b - child.c0 + 1, kstep * child.h)))
+                                        : (child.h <= (BAND2 - 2) / 2 || wave_sized(d, cx.tn, 2 * child.h, child.h));
+            child.soff = fr.soff + conv_submit<PREC>(cx, slot, fr.soff, csrc, cn, ch, coff, cout, cdst, 0.0, 0.0,
+                                                     child_wave);
+        }
         else if (!pop)
             child.soff = fr.soff;
         if (tid == 0) {
@@ -3104,6 +3147,7 @@ __device__ __forceinline__ void drive_option(const Desc &d, ll o, char *ws, cons
         *ret_sh = 0;
         *st_sh = Stats{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     }
+    __builtin_amdgcn_s_waitcnt(0);  // no staged input load of a previous option is still in flight
     __syncthreads();
     const ll ttot = clk();
     double p;
